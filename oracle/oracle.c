@@ -1,0 +1,451 @@
+/*
+ * FP64 CPU oracle of the physics-embedded cloth method (arXiv 2403.12820).
+ *
+ * TEST INFRASTRUCTURE ONLY. The tests, the smoke check and the CPU-baseline leg of
+ * the benchmark call it; the product library never does. It shares no code, header,
+ * table or constant with the GPU path.
+ *
+ * Plain loops in double precision, one cloth instance per call, written in the
+ * order the paper states each step:
+ *   - mass-spring step: section 3.1, eqs. (1) elastic spring force, (2) spring
+ *     damping, (4) gravity and air drag, (5) semi-implicit Euler with the
+ *     constraint operator (Dirichlet pins);
+ *   - physics-embedded CNN cell: section 3.2, eq. (6) one shared convolution
+ *     applied to the state and to its time derivative, eq. (7) linear, nonlinear
+ *     (ISRU) and derivative branches summed into a velocity increment, then
+ *     eq. (5) again as the embedded integrator (Fig. 2);
+ *   - its exact reverse mode (section 3.2.1: gradient backpropagation), the
+ *     data term of the eq. (8) loss and Adam (Table 1);
+ *   - FP64 diagnostics: position RMS error, energy, stretch ratio.
+ * Readings of passages the paper leaves open are listed in the design notes.
+ *
+ * State layout: six planes [x0 x1 x2 v0 v1 v2], each row-major H x W (node p = i*W + j).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ mass-spring */
+
+/* Section 3.1: springs of the 13-point stencil. Each node links to the 8 nodes of its
+   3x3 block and to the 4 nodes two steps away in the cardinal directions (the skip
+   links that give bending). Columns: row offset, column offset, family
+   (0 structural, rest length h; 1 shear, rest length sqrt(2) h; 2 bend, rest length 2h). */
+static const int OR_NB[12][3] = {
+    {0, 1, 0}, {0, -1, 0}, {1, 0, 0}, {-1, 0, 0},
+    {1, 1, 1}, {1, -1, 1}, {-1, 1, 1}, {-1, -1, 1},
+    {0, 2, 2}, {0, -2, 2}, {2, 0, 2}, {-2, 0, 2}};
+
+typedef struct {
+    double k[3];  /* spring constant per family (E of eq. 1) */
+    double mu;    /* damping coefficient of eq. (2) */
+    double drag;  /* air-drag coefficient d of eq. (4) */
+    double g[3];  /* gravity acceleration of eq. (4) */
+    double dt;    /* time step of eq. (5) */
+} or_ms_params;
+
+static double or_dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Total force on each node, f[3][H*W]; pinned nodes get zero.
+   f_i = m (g + a_ext) - d v_i + sum_j [ -k_j (r - L_j) x_ij / r - mu ((v_ij . x_ij)/r^2) x_ij ]
+   with x_ij = x_i - x_j, v_ij = v_i - v_j, r = |x_ij|. */
+void or_ms_force(int H, int W, double h, double m, const double *a_ext, const or_ms_params *P,
+                 const uint8_t *pin, const double *s, double *f)
+{
+    const long n = (long)H * W;
+    const double L[3] = {h, sqrt(2.0) * h, 2.0 * h};
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const long p = (long)i * W + j;
+            double F[3] = {0.0, 0.0, 0.0};
+            if (!pin[p]) {
+                for (int a = 0; a < 3; ++a)
+                    F[a] = m * (P->g[a] + a_ext[a]) - P->drag * s[(3 + a) * n + p]; /* eq. (4) + wind */
+                for (int q = 0; q < 12; ++q) {
+                    const int ii = i + OR_NB[q][0], jj = j + OR_NB[q][1];
+                    if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue; /* spring needs both ends */
+                    const long pj = (long)ii * W + jj;
+                    const int fam = OR_NB[q][2];
+                    double xij[3], vij[3];
+                    for (int a = 0; a < 3; ++a) {
+                        xij[a] = s[a * n + p] - s[a * n + pj];
+                        vij[a] = s[(3 + a) * n + p] - s[(3 + a) * n + pj];
+                    }
+                    const double r = sqrt(or_dot3(xij, xij));
+                    if (r < 1e-12 * h) continue;
+                    const double ce = -P->k[fam] * (r - L[fam]) / r;        /* eq. (1) */
+                    const double cd = -P->mu * or_dot3(vij, xij) / (r * r); /* eq. (2) */
+                    for (int a = 0; a < 3; ++a) F[a] += (ce + cd) * xij[a];
+                }
+            }
+            for (int a = 0; a < 3; ++a) f[a * n + p] = F[a];
+        }
+}
+
+/* One step of eq. (5): v' = C(v + dt f / m), x' = x + dt v'; C zeroes pinned velocities. */
+void or_ms_step(int H, int W, double h, double m, const double *a_ext, const or_ms_params *P,
+                const uint8_t *pin, const double *s, double *out)
+{
+    const long n = (long)H * W;
+    double *f = (double *)malloc(sizeof(double) * 3 * n);
+    or_ms_force(H, W, h, m, a_ext, P, pin, s, f);
+    for (long p = 0; p < n; ++p)
+        for (int a = 0; a < 3; ++a) {
+            const double v = pin[p] ? 0.0 : s[(3 + a) * n + p] + P->dt * f[a * n + p] / m;
+            out[(3 + a) * n + p] = v;
+            out[a * n + p] = s[a * n + p] + P->dt * v;
+        }
+    free(f);
+}
+
+/* n_steps consecutive steps; s is overwritten with the final state. */
+void or_ms_run(int H, int W, double h, double m, const double *a_ext, const or_ms_params *P,
+               const uint8_t *pin, double *s, int n_steps)
+{
+    const long n = (long)H * W;
+    double *t = (double *)malloc(sizeof(double) * 6 * n);
+    for (int k = 0; k < n_steps; ++k) {
+        or_ms_step(H, W, h, m, a_ext, P, pin, s, t);
+        memcpy(s, t, sizeof(double) * 6 * n);
+    }
+    free(t);
+}
+
+/* ------------------------------------------------------------------ diagnostics */
+
+/* Energy: kinetic + spring (each spring once) - potential of gravity and wind. */
+double or_energy(int H, int W, double h, double m, const double *a_ext, const or_ms_params *P,
+                 const double *s)
+{
+    const long n = (long)H * W;
+    const double L[3] = {h, sqrt(2.0) * h, 2.0 * h};
+    double e = 0.0;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const long p = (long)i * W + j;
+            for (int a = 0; a < 3; ++a) {
+                const double v = s[(3 + a) * n + p];
+                e += 0.5 * m * v * v - m * (P->g[a] + a_ext[a]) * s[a * n + p];
+            }
+            for (int q = 0; q < 12; ++q) {
+                /* count each spring once: take the offsets pointing "forward" */
+                const int di = OR_NB[q][0], dj = OR_NB[q][1];
+                if (!(di > 0 || (di == 0 && dj > 0))) continue;
+                const int ii = i + di, jj = j + dj;
+                if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
+                const long pj = (long)ii * W + jj;
+                double d[3];
+                for (int a = 0; a < 3; ++a) d[a] = s[a * n + p] - s[a * n + pj];
+                const double r = sqrt(or_dot3(d, d)) - L[OR_NB[q][2]];
+                e += 0.5 * P->k[OR_NB[q][2]] * r * r;
+            }
+        }
+    return e;
+}
+
+/* Largest r / L over structural springs (fam_mask bit f selects family f). */
+double or_max_stretch(int H, int W, double h, const double *s, int fam_mask)
+{
+    const long n = (long)H * W;
+    const double L[3] = {h, sqrt(2.0) * h, 2.0 * h};
+    double best = 0.0;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j)
+            for (int q = 0; q < 12; ++q) {
+                const int fam = OR_NB[q][2];
+                if (!((fam_mask >> fam) & 1)) continue;
+                const int ii = i + OR_NB[q][0], jj = j + OR_NB[q][1];
+                if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
+                double d[3];
+                for (int a = 0; a < 3; ++a) d[a] = s[a * n + (long)i * W + j] - s[a * n + (long)ii * W + jj];
+                const double r = sqrt(or_dot3(d, d)) / L[fam];
+                if (r > best) best = r;
+            }
+    return best;
+}
+
+/* Sum over nodes of |x - x_ref|^2 (the caller divides and takes the root). */
+double or_sq_pos_err(int H, int W, const double *s, const double *ref)
+{
+    const long n = (long)H * W;
+    double acc = 0.0;
+    for (long p = 0; p < n; ++p)
+        for (int a = 0; a < 3; ++a) {
+            const double d = s[a * n + p] - ref[a * n + p];
+            acc += d * d;
+        }
+    return acc;
+}
+
+/* ------------------------------------------------------------------ CNN cell */
+
+/* Parameter vector (row-major): conv K[Ch][6][3][3] | A[Ch][Ch] | B[Ch][Ch] |
+   W_L[3][Ch] | W_N[3][Ch] | W_D[3][Ch] | b_L[3]. */
+typedef struct { long K, A, B, WL, WN, WD, bL, total; } or_layout;
+
+static or_layout or_theta_layout(int ch)
+{
+    or_layout l;
+    l.K = 0;
+    l.A = l.K + (long)ch * 54;
+    l.B = l.A + (long)ch * ch;
+    l.WL = l.B + (long)ch * ch;
+    l.WN = l.WL + 3L * ch;
+    l.WD = l.WN + 3L * ch;
+    l.bL = l.WD + 3L * ch;
+    l.total = l.bL + 3;
+    return l;
+}
+
+long or_theta_size(int ch) { return or_theta_layout(ch).total; }
+
+static int or_clamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* bfloat16 round-to-nearest-even of a float value, returned as double. */
+static double or_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x; /* inf / nan unchanged */
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* ISRU with parameter alpha (section 3.2): sigma(z) = z / sqrt(1 + alpha z^2). */
+static double or_isru(double z, double al) { return z / sqrt(1.0 + al * z * z); }
+static double or_isru_d(double z, double al) { double t = 1.0 + al * z * z; return 1.0 / (t * sqrt(t)); }
+
+/* Input operator of the convolution for node (i, j): for each channel c and tap
+   o = (dy, dx) in {-1, 0, 1}^2 the neighbour q = clamp(i+dy, j+dx) is read; position
+   channels give the two-point difference with the central point S_c(q) - S_c(p)
+   (section 3.2: correlations of each neighbour with the centre), velocity channels the
+   raw value S_c(q). u[c*9 + (dy+1)*3 + (dx+1)].
+   'emu' != 0 emulates a float32 subtraction before the value is used. */
+static void or_im2col(int H, int W, const double *s, int i, int j, double *u, int emu)
+{
+    const long n = (long)H * W;
+    const long p = (long)i * W + j;
+    for (int c = 0; c < 6; ++c)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const long q = (long)or_clamp(i + dy, 0, H - 1) * W + or_clamp(j + dx, 0, W - 1);
+                double v = s[c * n + q];
+                if (c < 3) {
+                    v -= s[c * n + p];
+                    if (emu) v = (double)(float)v;
+                }
+                u[c * 9 + (dy + 1) * 3 + (dx + 1)] = v;
+            }
+}
+
+/* Forward quantities of the cell at one node, kept for the reverse pass. */
+typedef struct {
+    double uk[54], ud[54];             /* im2col of S^k and of S^k - S^{k-1} */
+    double phi[64], xi[64];            /* eq. (6): conv of the state and of its time difference */
+    double a[64], b[64], z[64];        /* z = (A phi) * (B phi) */
+    double gs[64], nn[64], dd[64];     /* sigma(phi), sigma(z), xi * sigma(phi) */
+    double dv[3];                      /* eq. (7): L + N + D */
+} or_node;
+
+/* emu bit 0: round conv operands (im2col entries and K) to bf16;
+   bit 1: round the operands of the two Ch x Ch maps (phi, A, B) to bf16;
+   bit 2: round the head operands (phi, n, d and W_L, W_N, W_D) to bf16. */
+static void or_cell_node(int H, int W, int ch, double alpha, const double *th, const or_layout *Lo,
+                         const double *sk, const double *dS, int i, int j, int emu, or_node *o)
+{
+    const int e0 = emu & 1, e1 = (emu >> 1) & 1, e2 = (emu >> 2) & 1;
+    or_im2col(H, W, sk, i, j, o->uk, e0);
+    or_im2col(H, W, dS, i, j, o->ud, e0);
+    if (e0)
+        for (int t = 0; t < 54; ++t) { o->uk[t] = or_bf16(o->uk[t]); o->ud[t] = or_bf16(o->ud[t]); }
+    for (int c = 0; c < ch; ++c) {
+        double pk = 0.0, pd = 0.0;
+        for (int t = 0; t < 54; ++t) {
+            const double w = e0 ? or_bf16(th[Lo->K + (long)c * 54 + t]) : th[Lo->K + (long)c * 54 + t];
+            pk += w * o->uk[t];
+            pd += w * o->ud[t];
+        }
+        o->phi[c] = pk;
+        o->xi[c] = pd;
+    }
+    for (int r = 0; r < ch; ++r) {
+        double sa = 0.0, sb = 0.0;
+        for (int c = 0; c < ch; ++c) {
+            const double ph = e1 ? or_bf16(o->phi[c]) : o->phi[c];
+            const double wa = th[Lo->A + (long)r * ch + c], wb = th[Lo->B + (long)r * ch + c];
+            sa += (e1 ? or_bf16(wa) : wa) * ph;
+            sb += (e1 ? or_bf16(wb) : wb) * ph;
+        }
+        o->a[r] = sa;
+        o->b[r] = sb;
+        o->z[r] = sa * sb;
+    }
+    for (int c = 0; c < ch; ++c) {
+        o->gs[c] = or_isru(o->phi[c], alpha);
+        o->nn[c] = or_isru(o->z[c], alpha);
+        o->dd[c] = o->xi[c] * o->gs[c];
+    }
+    for (int r = 0; r < 3; ++r) {
+        double acc = th[Lo->bL + r];
+        for (int c = 0; c < ch; ++c) {
+            double wl = th[Lo->WL + r * ch + c], wn = th[Lo->WN + r * ch + c], wd = th[Lo->WD + r * ch + c];
+            double fp = o->phi[c], fn = o->nn[c], fd = o->dd[c];
+            if (e2) {
+                wl = or_bf16(wl); wn = or_bf16(wn); wd = or_bf16(wd);
+                fp = or_bf16(fp); fn = or_bf16(fn); fd = or_bf16(fd);
+            }
+            acc += wl * fp + wn * fn + wd * fd;
+        }
+        o->dv[r] = acc;
+    }
+}
+
+/* Time difference S^k - S^{k-1} of the six planes (emu: rounded like a float32 subtraction). */
+static double *or_time_diff(long n, const double *sp, const double *sk, int emu)
+{
+    double *d = (double *)malloc(sizeof(double) * 6 * n);
+    for (long t = 0; t < 6 * n; ++t) {
+        d[t] = sk[t] - sp[t];
+        if (emu) d[t] = (double)(float)d[t];
+    }
+    return d;
+}
+
+/* One frame of the framework (Fig. 2): the cell gives dv, then eq. (5) with the pins and the
+   hard-encoded wind: v' = C(v + dv + dt a_ext), x' = x + dt v'. */
+void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double *a_ext,
+                    const uint8_t *pin, const double *theta, const double *s_prev,
+                    const double *s_cur, double *s_next, int emu, double *dv_out)
+{
+    const long n = (long)H * W;
+    const or_layout Lo = or_theta_layout(ch);
+    double *dS = or_time_diff(n, s_prev, s_cur, emu & 1);
+    or_node *o = (or_node *)malloc(sizeof(or_node));
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const long p = (long)i * W + j;
+            or_cell_node(H, W, ch, alpha, theta, &Lo, s_cur, dS, i, j, emu, o);
+            for (int a = 0; a < 3; ++a) {
+                if (dv_out) dv_out[a * n + p] = o->dv[a];
+                const double v = pin[p] ? 0.0 : s_cur[(3 + a) * n + p] + o->dv[a] + dt * a_ext[a];
+                s_next[(3 + a) * n + p] = v;
+                s_next[a * n + p] = s_cur[a * n + p] + dt * v;
+            }
+        }
+    free(o);
+    free(dS);
+}
+
+/* Reverse mode of or_cnn_forward (emu = 0). Given g_next = dLoss/dS^{k+1}, accumulate
+   dLoss/dS^k into g_cur, dLoss/dS^{k-1} into g_prev and dLoss/dtheta into g_theta. */
+void or_cnn_backward(int H, int W, int ch, double alpha, double dt, const uint8_t *pin,
+                     const double *theta, const double *s_prev, const double *s_cur,
+                     const double *g_next, double *g_cur, double *g_prev, double *g_theta)
+{
+    const long n = (long)H * W;
+    const or_layout Lo = or_theta_layout(ch);
+    double *dS = or_time_diff(n, s_prev, s_cur, 0);
+    or_node *o = (or_node *)malloc(sizeof(or_node));
+    double gdv[3], gphi[64], gxi[64], gnn[64], gdd[64], gz[64], ga[64], gb[64], guk[54], gud[54];
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const long p = (long)i * W + j;
+            or_cell_node(H, W, ch, alpha, theta, &Lo, s_cur, dS, i, j, 0, o);
+            /* eq. (5): x' = x + dt v', v' = (1 - pin)(v + dv + dt a) */
+            for (int a = 0; a < 3; ++a) {
+                const double gvt = g_next[(3 + a) * n + p] + dt * g_next[a * n + p];
+                g_cur[a * n + p] += g_next[a * n + p];
+                gdv[a] = pin[p] ? 0.0 : gvt;
+                g_cur[(3 + a) * n + p] += gdv[a];
+            }
+            /* eq. (7) heads */
+            for (int c = 0; c < ch; ++c) { gphi[c] = 0.0; gnn[c] = 0.0; gdd[c] = 0.0; }
+            for (int r = 0; r < 3; ++r) {
+                g_theta[Lo.bL + r] += gdv[r];
+                for (int c = 0; c < ch; ++c) {
+                    g_theta[Lo.WL + r * ch + c] += gdv[r] * o->phi[c];
+                    g_theta[Lo.WN + r * ch + c] += gdv[r] * o->nn[c];
+                    g_theta[Lo.WD + r * ch + c] += gdv[r] * o->dd[c];
+                    gphi[c] += theta[Lo.WL + r * ch + c] * gdv[r];
+                    gnn[c] += theta[Lo.WN + r * ch + c] * gdv[r];
+                    gdd[c] += theta[Lo.WD + r * ch + c] * gdv[r];
+                }
+            }
+            /* derivative branch d = xi * sigma(phi); nonlinear branch n = sigma(z) */
+            for (int c = 0; c < ch; ++c) {
+                gxi[c] = gdd[c] * o->gs[c];
+                gphi[c] += gdd[c] * o->xi[c] * or_isru_d(o->phi[c], alpha);
+                gz[c] = gnn[c] * or_isru_d(o->z[c], alpha);
+                ga[c] = gz[c] * o->b[c];
+                gb[c] = gz[c] * o->a[c];
+            }
+            for (int r = 0; r < ch; ++r)
+                for (int c = 0; c < ch; ++c) {
+                    g_theta[Lo.A + (long)r * ch + c] += ga[r] * o->phi[c];
+                    g_theta[Lo.B + (long)r * ch + c] += gb[r] * o->phi[c];
+                    gphi[c] += theta[Lo.A + (long)r * ch + c] * ga[r] + theta[Lo.B + (long)r * ch + c] * gb[r];
+                }
+            /* eq. (6) conv */
+            for (int t = 0; t < 54; ++t) { guk[t] = 0.0; gud[t] = 0.0; }
+            for (int c = 0; c < ch; ++c)
+                for (int t = 0; t < 54; ++t) {
+                    const double w = theta[Lo.K + (long)c * 54 + t];
+                    g_theta[Lo.K + (long)c * 54 + t] += gphi[c] * o->uk[t] + gxi[c] * o->ud[t];
+                    guk[t] += w * gphi[c];
+                    gud[t] += w * gxi[c];
+                }
+            /* adjoint of the input operator: the tap value of (c, o) came from S_c(q) and, for
+               positions, minus S_c(p); the time difference is S^k - S^{k-1}. */
+            for (int c = 0; c < 6; ++c)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int t = c * 9 + (dy + 1) * 3 + (dx + 1);
+                        const long q = (long)or_clamp(i + dy, 0, H - 1) * W + or_clamp(j + dx, 0, W - 1);
+                        g_cur[c * n + q] += guk[t] + gud[t];
+                        g_prev[c * n + q] -= gud[t];
+                        if (c < 3) {
+                            g_cur[c * n + p] -= guk[t] + gud[t];
+                            g_prev[c * n + p] += gud[t];
+                        }
+                    }
+        }
+    free(o);
+    free(dS);
+}
+
+/* ------------------------------------------------------------------ loss and Adam */
+
+/* Data term of eq. (8), normalised per field: w / n_free * sum over free nodes of
+   |x_hat - x|^2 / sx^2 + |v_hat - v|^2 / sv^2. Adds d/ds_hat into g (if non-null). */
+double or_loss_mse(long n, const uint8_t *pin, long n_free, double sx, double sv, double w,
+                   const double *s_hat, const double *s_true, double *g)
+{
+    double acc = 0.0;
+    for (int c = 0; c < 6; ++c) {
+        const double sc = c < 3 ? sx : sv;
+        for (long p = 0; p < n; ++p) {
+            if (pin[p]) continue;
+            const double d = s_hat[c * n + p] - s_true[c * n + p];
+            acc += d * d / (sc * sc);
+            if (g) g[c * n + p] += w * 2.0 * d / (sc * sc * (double)n_free);
+        }
+    }
+    return w * acc / (double)n_free;
+}
+
+/* Adam (Kingma and Ba), step t >= 1, bias-corrected. */
+void or_adam(long n, double lr, double b1, double b2, double eps, int t, double *th, double *m,
+             double *v, const double *g)
+{
+    for (long i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        const double mh = m[i] / (1.0 - pow(b1, t));
+        const double vh = v[i] / (1.0 - pow(b2, t));
+        th[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
