@@ -1,0 +1,699 @@
+// C ABI of the pecnn library: argument validation, plans, workspace queries, the rollout
+// orchestration (hipGraph-captured chunks with a per-instance guard and fall-back to the
+// mass-spring step) and the tile autotuner.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <functional>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pecnn {
+// kernels in the other translation units
+MsParamsDev ms_params_dev(const cloth_ms_params* p);
+int ms_step_once(const pecnn_plan*, int cfg, const MsParamsDev&, const float*, float*, const uint8_t*, hipStream_t);
+int ms_step_run(const pecnn_plan*, int cfg, const MsParamsDev&, const float*, float*, float*, int,
+                const uint8_t*, hipStream_t);
+int cnn_forward_launch(const pecnn_plan*, int cfg, const pecnn_model*, const float*, const float*, float*,
+                       const int32_t*, hipStream_t);
+size_t backward_ws_bytes(const pecnn_plan*, int ch);
+int backward_launch(const pecnn_plan*, const pecnn_model*, const float*, const float*, const float*, float*,
+                    float*, float*, void*, hipStream_t);
+size_t reduce_ws_bytes(const pecnn_plan*);
+int reduce_launch(const pecnn_plan*, const MsParamsDev&, const float*, const float*, double*, void*, hipStream_t);
+int loss_launch(const pecnn_plan*, const float*, const float*, float, float, float, int64_t, double*, float*, void*,
+                hipStream_t);
+int adam_launch(int64_t, float, float, float, float, int, float*, float*, float*, const float*, hipStream_t);
+int gather_launch(const float*, int64_t, int, const int64_t*, int, const int32_t*, const int32_t*, int, int, int,
+                  float*, hipStream_t);
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return PECNN_E_HIP;
+}
+
+int num_cus() {
+  static int cached = 0;
+  if (cached == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cached = n;
+    else
+      cached = 256;
+  }
+  return cached;
+}
+
+static bool finite_pos(float x) { return isfinite(x) && x > 0.f; }
+static bool finite_nonneg(float x) { return isfinite(x) && x >= 0.f; }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int check_ms_params(const cloth_ms_params* p) {
+  if (!p) { set_error("null cloth_ms_params"); return PECNN_E_INVALID; }
+  if (!finite_nonneg(p->k_struct) || !finite_nonneg(p->k_shear) || !finite_nonneg(p->k_bend) ||
+      !finite_nonneg(p->mu) || !finite_nonneg(p->drag) || !finite_pos(p->dt) || !isfinite(p->g[0]) ||
+      !isfinite(p->g[1]) || !isfinite(p->g[2])) {
+    set_error("cloth_ms_params: spring constants, damping and drag must be finite and >= 0, dt finite and > 0");
+    return PECNN_E_INVALID;
+  }
+  return PECNN_OK;
+}
+
+static int check_model(const pecnn_model* m) {
+  if (!m || !m->theta) { set_error("null model or theta"); return PECNN_E_INVALID; }
+  if (m->ch != 16 && m->ch != 32) { set_error("channel count %d unsupported (16 or 32)", m->ch); return PECNN_E_UNSUPPORTED; }
+  if (m->precision != PECNN_FP32 && m->precision != PECNN_BF16) { set_error("precision %d unsupported", m->precision); return PECNN_E_UNSUPPORTED; }
+  if (!finite_pos(m->dt) || !finite_pos(m->isru_alpha)) { set_error("model dt and isru_alpha must be finite and > 0"); return PECNN_E_INVALID; }
+  return PECNN_OK;
+}
+
+static int check_plan(const pecnn_plan* plan) {
+  if (!plan || !plan->d_inst) { set_error("null plan"); return PECNN_E_INVALID; }
+  return PECNN_OK;
+}
+
+// ---------------------------------------------------------------- rollout graph cache
+struct GraphKey {
+  const void* buf[4];
+  int len, with_ms, guard, ms_cfg, cnn_cfg, ch, prec, substeps;
+  float dt, alpha;
+  const float* theta;
+  cloth_ms_params sim;
+  pecnn_guard gd;
+  const int32_t* fallback;
+  const void* ws;
+  const double* stats;
+  bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
+struct GraphCache {
+  std::vector<GraphEntry> entries;
+  hipStream_t capture = nullptr;
+  int* host_count = nullptr;
+};
+
+static void graph_cache_free(pecnn_plan* plan) {
+  GraphCache* gc = (GraphCache*)plan->graph_cache;
+  if (!gc) return;
+  for (auto& e : gc->entries) (void)hipGraphExecDestroy(e.exec);
+  if (gc->capture) (void)hipStreamDestroy(gc->capture);
+  if (gc->host_count) (void)hipHostFree(gc->host_count);
+  delete gc;
+  plan->graph_cache = nullptr;
+}
+
+// ---------------------------------------------------------------- guard kernels
+// Every check: per instance, compare the largest structural stretch ratio and the energy gain
+// with the guard's bounds; a tripped instance falls back for good. Also counts fallen instances.
+// count[0] receives the number of fallen instances, count[1] keeps the index of the check.
+__global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restrict__ now, double* __restrict__ e0,
+                                                    const double* __restrict__ eref, pecnn_guard G, int init,
+                                                    int32_t* __restrict__ fallback, uint8_t* __restrict__ active_ms,
+                                                    double* __restrict__ stats, int* __restrict__ count) {
+  __shared__ int sh[256];
+  const int chk = init ? 0 : count[1] + 1;
+  const int step = chk * G.check_every;
+  int cnt = 0;
+  for (int b = threadIdx.x; b < n; b += 256) {
+    const double e = now[4 * b + 1], st = now[4 * b + 2];
+    if (init) {
+      e0[b] = e;
+      stats[4 * b + 0] = e;
+      stats[4 * b + 2] = st;
+      stats[4 * b + 3] = fallback[b] ? 0.0 : -1.0;
+    } else if (fallback[b] == 0 &&
+               (!(st <= (double)G.stretch_max) || !((e - e0[b]) / eref[b] <= (double)G.energy_gain_max))) {
+      fallback[b] = 1;
+      stats[4 * b + 3] = step;
+    }
+    stats[4 * b + 1] = e;
+    stats[4 * b + 2] = fmax(stats[4 * b + 2], st);
+    active_ms[b] = fallback[b] != 0;
+    cnt += fallback[b] != 0;
+  }
+  sh[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    count[0] = sh[0];
+    count[1] = chk;
+  }
+}
+
+struct RolloutWs {
+  float* X;        // third rotating state
+  float* T;        // mass-spring substep temporary
+  double* part;    // reduction partials
+  double* now;     // [4n] diagnostics of the current check
+  double* e0;      // [n] energy at the start
+  double* eref;    // [n] energy scale
+  double* stats;   // [4n] used when the caller passes NULL
+  uint8_t* active; // [n]
+  int* count;      // [1]
+  size_t bytes;
+};
+
+static RolloutWs rollout_layout(const pecnn_plan* plan, void* base) {
+  RolloutWs w;
+  char* p = (char*)base;
+  size_t o = 0;
+  const size_t st = align256(6 * (size_t)plan->total * sizeof(float));
+  w.X = (float*)(p + o); o += st;
+  w.T = (float*)(p + o); o += st;
+  w.part = (double*)(p + o); o += align256(reduce_ws_bytes(plan));
+  w.now = (double*)(p + o); o += align256(4 * (size_t)plan->n * sizeof(double));
+  w.e0 = (double*)(p + o); o += align256((size_t)plan->n * sizeof(double));
+  w.eref = (double*)(p + o); o += align256((size_t)plan->n * sizeof(double));
+  w.stats = (double*)(p + o); o += align256(4 * (size_t)plan->n * sizeof(double));
+  w.active = (uint8_t*)(p + o); o += align256((size_t)plan->n);
+  w.count = (int*)(p + o); o += 256;
+  w.bytes = o;
+  return w;
+}
+
+}  // namespace pecnn
+
+using namespace pecnn;
+
+extern "C" {
+
+int32_t pecnn_version(void) { return 1; }
+
+const char* pecnn_status_string(int s) {
+  switch (s) {
+    case PECNN_OK: return "ok";
+    case PECNN_E_INVALID: return "invalid argument";
+    case PECNN_E_SHAPE: return "inconsistent shape";
+    case PECNN_E_UNSUPPORTED: return "unsupported configuration";
+    case PECNN_E_WORKSPACE: return "workspace missing or too small";
+    case PECNN_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* pecnn_last_error(void) { return g_err; }
+
+int64_t pecnn_theta_size(int32_t ch) {
+  if (ch <= 0 || ch > 64) return -1;
+  return (int64_t)ch * 54 + 2 * (int64_t)ch * ch + 9 * (int64_t)ch + 3;
+}
+
+static int check_desc(const pecnn_batch_desc* d) {
+  if (!d || !d->H || !d->W || !d->h || !d->mass || !d->a_ext) { set_error("null batch description"); return PECNN_E_INVALID; }
+  if (d->n < 1 || d->n > 65536) { set_error("instance count %d out of range", d->n); return PECNN_E_SHAPE; }
+  int64_t tot = 0;
+  for (int b = 0; b < d->n; ++b) {
+    const int64_t hw = (int64_t)d->H[b] * d->W[b];
+    if (d->H[b] < 1 || d->W[b] < 1 || hw < 2 || hw >= (1 << 24)) {
+      set_error("instance %d: grid %d x %d out of range", b, d->H[b], d->W[b]);
+      return PECNN_E_SHAPE;
+    }
+    if (!finite_pos(d->h[b]) || !finite_pos(d->mass[b]) || !isfinite(d->a_ext[3 * b]) ||
+        !isfinite(d->a_ext[3 * b + 1]) || !isfinite(d->a_ext[3 * b + 2])) {
+      set_error("instance %d: spacing and mass must be finite and > 0, a_ext finite", b);
+      return PECNN_E_INVALID;
+    }
+    tot += hw;
+  }
+  if (tot >= ((int64_t)1 << 31) / 6) { set_error("batch too large (%lld nodes)", (long long)tot); return PECNN_E_SHAPE; }
+  return PECNN_OK;
+}
+
+static void tile_counts(const pecnn_batch_desc* d, std::vector<int64_t>& ntile) {
+  ntile.assign(kNumCfg, 0);
+  for (int b = 0; b < d->n; ++b) {
+    for (int c = 0; c < kNumMsCfg; ++c) ntile[ms_cfg_slot(c)] += tiles_of(d->H[b], d->W[b], kMsCfg[c].tx, kMsCfg[c].ty);
+    for (int c = 0; c < kNumCnnCfg; ++c) ntile[cnn_cfg_slot(c)] += tiles_of(d->H[b], d->W[b], kCnnCfg[c].tx, kCnnCfg[c].ty);
+    ntile[kCfgChunk] += ((int64_t)d->H[b] * d->W[b] + kChunk - 1) / kChunk;
+  }
+}
+
+int pecnn_plan_device_bytes(const pecnn_batch_desc* d, size_t* bytes) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!bytes) { set_error("null bytes"); return PECNN_E_INVALID; }
+  *bytes = align256((size_t)d->n * sizeof(InstDev)) + kNumCfg * align256((size_t)(d->n + 1) * sizeof(int32_t));
+  return PECNN_OK;
+}
+
+int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_mem, size_t dev_bytes, void* stream,
+                      pecnn_plan** out) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!pin || !dev_mem || !out) { set_error("null pin, plan memory or output handle"); return PECNN_E_INVALID; }
+  size_t need = 0;
+  pecnn_plan_device_bytes(d, &need);
+  if (dev_bytes < need) { set_error("plan memory %zu < %zu bytes", dev_bytes, need); return PECNN_E_WORKSPACE; }
+  std::vector<int64_t> nt;
+  tile_counts(d, nt);
+  for (int c = 0; c < kNumCfg; ++c)
+    if (nt[c] >= ((int64_t)1 << 31)) { set_error("too many tiles"); return PECNN_E_SHAPE; }
+
+  const int n = d->n;
+  std::vector<char> host(need, 0);
+  InstDev* hi = (InstDev*)host.data();
+  int64_t off = 0;
+  int max_hw = 0;
+  for (int b = 0; b < n; ++b) {
+    hi[b].H = d->H[b];
+    hi[b].W = d->W[b];
+    hi[b].off = off;
+    hi[b].h = d->h[b];
+    hi[b].mass = d->mass[b];
+    hi[b].ax = d->a_ext[3 * b];
+    hi[b].ay = d->a_ext[3 * b + 1];
+    hi[b].az = d->a_ext[3 * b + 2];
+    hi[b].pad = 0;
+    off += (int64_t)d->H[b] * d->W[b];
+    if (d->H[b] * d->W[b] > max_hw) max_hw = d->H[b] * d->W[b];
+  }
+  size_t o = align256((size_t)n * sizeof(InstDev));
+  size_t pre_off[kNumCfg];
+  for (int c = 0; c < kNumCfg; ++c) {
+    pre_off[c] = o;
+    int32_t* pre = (int32_t*)(host.data() + o);
+    int32_t acc = 0;
+    for (int b = 0; b < n; ++b) {
+      pre[b] = acc;
+      int tiles;
+      if (c < kNumMsCfg) tiles = tiles_of(d->H[b], d->W[b], kMsCfg[c].tx, kMsCfg[c].ty);
+      else if (c < kNumMsCfg + kNumCnnCfg) tiles = tiles_of(d->H[b], d->W[b], kCnnCfg[c - kNumMsCfg].tx, kCnnCfg[c - kNumMsCfg].ty);
+      else tiles = (int)(((int64_t)d->H[b] * d->W[b] + kChunk - 1) / kChunk);
+      acc += tiles;
+    }
+    pre[n] = acc;
+    o += align256((size_t)(n + 1) * sizeof(int32_t));
+  }
+  hipStream_t st = (hipStream_t)stream;
+  PECNN_HIP(hipMemcpyAsync(dev_mem, host.data(), need, hipMemcpyHostToDevice, st));
+  PECNN_HIP(hipStreamSynchronize(st));
+
+  pecnn_plan* p = (pecnn_plan*)calloc(1, sizeof(pecnn_plan));
+  if (!p) { set_error("out of host memory"); return PECNN_E_INVALID; }
+  p->n = n;
+  p->total = off;
+  p->H = (int32_t*)malloc(sizeof(int32_t) * n);
+  p->W = (int32_t*)malloc(sizeof(int32_t) * n);
+  p->off = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  p->h = (float*)malloc(sizeof(float) * n);
+  p->mass = (float*)malloc(sizeof(float) * n);
+  p->a_ext = (float*)malloc(sizeof(float) * 3 * n);
+  if (!p->H || !p->W || !p->off || !p->h || !p->mass || !p->a_ext) {
+    pecnn_plan_destroy(p);
+    set_error("out of host memory");
+    return PECNN_E_INVALID;
+  }
+  for (int b = 0; b < n; ++b) {
+    p->H[b] = d->H[b];
+    p->W[b] = d->W[b];
+    p->off[b] = hi[b].off;
+    p->h[b] = d->h[b];
+    p->mass[b] = d->mass[b];
+    for (int a = 0; a < 3; ++a) p->a_ext[3 * b + a] = d->a_ext[3 * b + a];
+  }
+  p->off[n] = off;
+  p->pin = pin;
+  p->d_inst = (InstDev*)dev_mem;
+  for (int c = 0; c < kNumCfg; ++c) {
+    p->d_prefix[c] = (int32_t*)((char*)dev_mem + pre_off[c]);
+    p->n_tiles[c] = (int32_t)nt[c];
+  }
+  // defaults: wide rows for large instances, square tiles when most instances are small
+  p->ms_cfg = max_hw >= 64 * 64 ? 3 : 2;
+  p->cnn_cfg = max_hw >= 64 * 64 ? 0 : 2;
+  p->max_hw = max_hw;
+  p->graph_cache = nullptr;
+  *out = p;
+  return PECNN_OK;
+}
+
+int pecnn_plan_destroy(pecnn_plan* p) {
+  if (!p) return PECNN_OK;
+  graph_cache_free(p);
+  free(p->H);
+  free(p->W);
+  free(p->off);
+  free(p->h);
+  free(p->mass);
+  free(p->a_ext);
+  free(p);
+  return PECNN_OK;
+}
+
+int64_t pecnn_plan_nodes(const pecnn_plan* p) { return p ? p->total : -1; }
+
+int pecnn_plan_set_tiles(pecnn_plan* p, int32_t ms_cfg, int32_t cnn_cfg) {
+  if (check_plan(p)) return PECNN_E_INVALID;
+  if (ms_cfg < -1 || ms_cfg >= kNumMsCfg || cnn_cfg < -1 || cnn_cfg >= kNumCnnCfg) {
+    set_error("tile configuration out of range");
+    return PECNN_E_INVALID;
+  }
+  if (ms_cfg >= 0) p->ms_cfg = ms_cfg;
+  if (cnn_cfg >= 0) p->cnn_cfg = cnn_cfg;
+  return PECNN_OK;
+}
+
+int pecnn_plan_get_tiles(const pecnn_plan* p, int32_t* ms_cfg, int32_t* cnn_cfg) {
+  if (check_plan(p) || !ms_cfg || !cnn_cfg) { set_error("null argument"); return PECNN_E_INVALID; }
+  *ms_cfg = p->ms_cfg;
+  *cnn_cfg = p->cnn_cfg;
+  return PECNN_OK;
+}
+
+int pecnn_workspace_bytes(const pecnn_plan* p, const pecnn_model* m, int32_t which, size_t* bytes) {
+  if (check_plan(p) || !bytes) { set_error("null plan or bytes"); return PECNN_E_INVALID; }
+  switch (which) {
+    case PECNN_WS_MS_STEP: *bytes = align256(6 * (size_t)p->total * sizeof(float)); return PECNN_OK;
+    case PECNN_WS_REDUCE: *bytes = align256(reduce_ws_bytes(p)); return PECNN_OK;
+    case PECNN_WS_BACKWARD: {
+      int rc = check_model(m);
+      if (rc) return rc;
+      *bytes = align256(backward_ws_bytes(p, m->ch));
+      return PECNN_OK;
+    }
+    case PECNN_WS_ROLLOUT: *bytes = rollout_layout(p, nullptr).bytes; return PECNN_OK;
+    default: set_error("unknown workspace kind %d", which); return PECNN_E_INVALID;
+  }
+}
+
+int cloth_ms_step(const pecnn_plan* p, const cloth_ms_params* prm, const float* s_in, float* s_out, int32_t n_steps,
+                  const uint8_t* active, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((rc = check_ms_params(prm))) return rc;
+  if (!s_in || !s_out) { set_error("null state"); return PECNN_E_INVALID; }
+  if (n_steps < 1) { set_error("n_steps must be >= 1"); return PECNN_E_INVALID; }
+  const size_t sb = 6 * (size_t)p->total * sizeof(float);
+  const char *a = (const char*)s_in, *b = (const char*)s_out;
+  if (a < b + sb && b < a + sb) { set_error("s_in and s_out overlap"); return PECNN_E_INVALID; }
+  if (n_steps > 1) {
+    if (!ws || ws_bytes < sb) { set_error("workspace of %zu bytes needed for n_steps > 1", sb); return PECNN_E_WORKSPACE; }
+    const char* w = (const char*)ws;
+    if ((w < a + sb && a < w + sb) || (w < b + sb && b < w + sb)) { set_error("workspace overlaps a state"); return PECNN_E_INVALID; }
+  }
+  return ms_step_run(p, p->ms_cfg, ms_params_dev(prm), s_in, s_out, (float*)ws, n_steps, active, (hipStream_t)stream);
+}
+
+int pecnn_forward(const pecnn_plan* p, const pecnn_model* m, const float* s_prev, const float* s_cur, float* s_next,
+                  void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((rc = check_model(m))) return rc;
+  if (!s_prev || !s_cur || !s_next) { set_error("null state"); return PECNN_E_INVALID; }
+  const size_t sb = 6 * (size_t)p->total * sizeof(float);
+  const char *a = (const char*)s_prev, *c = (const char*)s_cur, *n = (const char*)s_next;
+  if ((n < a + sb && a < n + sb) || (n < c + sb && c < n + sb)) { set_error("s_next overlaps an input"); return PECNN_E_INVALID; }
+  return cnn_forward_launch(p, p->cnn_cfg, m, s_prev, s_cur, s_next, nullptr, (hipStream_t)stream);
+}
+
+int pecnn_backward(const pecnn_plan* p, const pecnn_model* m, const float* s_prev, const float* s_cur,
+                   const float* g_next, float* g_cur, float* g_prev, float* g_theta, void* ws, size_t ws_bytes,
+                   void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((rc = check_model(m))) return rc;
+  if (m->precision != PECNN_FP32) { set_error("backward needs an FP32 model"); return PECNN_E_UNSUPPORTED; }
+  if (!s_prev || !s_cur || !g_next || !g_theta) { set_error("null state, gradient or theta gradient"); return PECNN_E_INVALID; }
+  if (g_cur && g_prev && g_cur == g_prev) { set_error("g_cur and g_prev must differ"); return PECNN_E_INVALID; }
+  const size_t need = align256(backward_ws_bytes(p, m->ch));
+  if (!ws || ws_bytes < need) { set_error("backward workspace of %zu bytes needed", need); return PECNN_E_WORKSPACE; }
+  return backward_launch(p, m, s_prev, s_cur, g_next, g_cur, g_prev, g_theta, ws, (hipStream_t)stream);
+}
+
+int cloth_reduce_fp64(const pecnn_plan* p, const cloth_ms_params* prm, const float* s, const float* s_ref, double* out,
+                      void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((rc = check_ms_params(prm))) return rc;
+  if (!s || !out) { set_error("null state or output"); return PECNN_E_INVALID; }
+  if (!ws || ws_bytes < reduce_ws_bytes(p)) { set_error("reduce workspace too small"); return PECNN_E_WORKSPACE; }
+  return reduce_launch(p, ms_params_dev(prm), s, s_ref, out, ws, (hipStream_t)stream);
+}
+
+int pecnn_loss_mse(const pecnn_plan* p, const float* s_hat, const float* s_true, float sx, float sv, float w,
+                   int64_t n_free, double* loss, float* g_hat, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!s_hat || !s_true || !loss) { set_error("null state or loss"); return PECNN_E_INVALID; }
+  if (!finite_pos(sx) || !finite_pos(sv) || !isfinite(w) || n_free < 1) {
+    set_error("scales must be finite and > 0, weight finite, n_free >= 1");
+    return PECNN_E_INVALID;
+  }
+  if (!ws || ws_bytes < reduce_ws_bytes(p)) { set_error("loss workspace too small"); return PECNN_E_WORKSPACE; }
+  return loss_launch(p, s_hat, s_true, sx, sv, w, n_free, loss, g_hat, ws, (hipStream_t)stream);
+}
+
+int pecnn_adam_step(int64_t n, float lr, float b1, float b2, float eps, int32_t t, float* th, float* m, float* v,
+                    const float* g, void* stream) {
+  if (!th || !m || !v || !g || n < 1) { set_error("null buffer or n < 1"); return PECNN_E_INVALID; }
+  if (!finite_pos(lr) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !finite_pos(eps) || t < 1) {
+    set_error("Adam: lr, eps > 0, betas in [0, 1), t >= 1");
+    return PECNN_E_INVALID;
+  }
+  return adam_launch(n, lr, b1, b2, eps, t, th, m, v, g, (hipStream_t)stream);
+}
+
+int pecnn_gather_windows(const float* traj, int64_t traj_nodes, int32_t n_saved, const int64_t* traj_off,
+                         int32_t n_traj, const int32_t* traj_inst, const int32_t* frame_idx, int32_t n_win,
+                         int32_t npw, int32_t n_frames, float* out, void* stream) {
+  if (!traj || !traj_off || !traj_inst || !frame_idx || !out) { set_error("null buffer"); return PECNN_E_INVALID; }
+  if (traj_nodes < 1 || n_saved < 1 || n_traj < 1 || n_win < 1 || npw < 1 || n_frames < 1 || n_win > 65535 ||
+      n_frames * 6 > 65535) {
+    set_error("gather sizes out of range");
+    return PECNN_E_SHAPE;
+  }
+  return gather_launch(traj, traj_nodes, n_saved, traj_off, n_traj, traj_inst, frame_idx, n_win, npw, n_frames, out,
+                       (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- rollout
+// Record the network steps of one chunk (and the guard check that ends it) on 'st'.
+static int record_chunk(pecnn_plan* p, const pecnn_model* m, const MsParamsDev& sim, const pecnn_guard* g,
+                        float* const buf[3], float* T, int len, bool with_ms, bool guard_on, int32_t* fallback,
+                        double* stats, const RolloutWs& w, hipStream_t st) {
+  float* P = buf[0];
+  float* C = buf[1];
+  float* X = buf[2];
+  for (int k = 0; k < len; ++k) {
+    int rc = cnn_forward_launch(p, p->cnn_cfg, m, P, C, X, fallback, st);
+    if (rc) return rc;
+    if (with_ms) {
+      rc = ms_step_run(p, p->ms_cfg, sim, C, X, T, g->substeps, w.active, st);
+      if (rc) return rc;
+    }
+    float* t = P;
+    P = C;
+    C = X;
+    X = t;
+  }
+  if (guard_on) {
+    int rc = reduce_launch(p, sim, C, nullptr, w.now, w.part, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, *g, 0, fallback,
+                       w.active, stats, w.count);
+    PECNN_LAUNCH_CHECK("guard_kernel");
+  }
+  return PECNN_OK;
+}
+
+int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* simp, const pecnn_guard* g,
+                  float* s_prev, float* s_cur, int32_t n_steps, int32_t* fallback, double* stats, void* ws,
+                  size_t ws_bytes, void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((rc = check_model(m))) return rc;
+  if ((rc = check_ms_params(simp))) return rc;
+  if (!g || !s_prev || !s_cur || !fallback) { set_error("null guard, state or fallback flags"); return PECNN_E_INVALID; }
+  if (n_steps < 0) { set_error("n_steps must be >= 0"); return PECNN_E_INVALID; }
+  if (g->substeps < 1 || g->substeps > 1000) { set_error("guard substeps must be in [1, 1000]"); return PECNN_E_INVALID; }
+  if (g->check_every > 0 && (!(g->stretch_max > 0.f) || isnan(g->energy_gain_max))) {
+    set_error("guard bounds must be > 0 / not NaN");
+    return PECNN_E_INVALID;
+  }
+  const size_t sb = 6 * (size_t)p->total * sizeof(float);
+  if (s_prev == s_cur || ((const char*)s_prev < (const char*)s_cur + sb && (const char*)s_cur < (const char*)s_prev + sb)) {
+    set_error("s_prev and s_cur overlap");
+    return PECNN_E_INVALID;
+  }
+  const RolloutWs w = rollout_layout(p, ws);
+  if (!ws || ws_bytes < w.bytes) { set_error("rollout workspace of %zu bytes needed", w.bytes); return PECNN_E_WORKSPACE; }
+  hipStream_t st = (hipStream_t)stream;
+  if (n_steps == 0) return PECNN_OK;
+  const MsParamsDev sim = ms_params_dev(simp);
+  double* stats_d = stats ? stats : w.stats;
+  const bool guard_on = g->check_every > 0;
+
+  GraphCache* gc = (GraphCache*)p->graph_cache;
+  if (!gc) {
+    gc = new GraphCache();
+    p->graph_cache = gc;
+    PECNN_HIP(hipStreamCreateWithFlags(&gc->capture, hipStreamNonBlocking));
+    PECNN_HIP(hipHostMalloc((void**)&gc->host_count, sizeof(int), hipHostMallocDefault));
+  }
+
+  // prologue: energy scale, starting diagnostics, fall-back mask
+  {
+    std::vector<double> eref(p->n);
+    const double gn = sqrt((double)simp->g[0] * simp->g[0] + (double)simp->g[1] * simp->g[1] + (double)simp->g[2] * simp->g[2]);
+    for (int b = 0; b < p->n; ++b) {
+      double e = (double)p->H[b] * p->W[b] * p->mass[b] * (gn > 0 ? gn : 1.0) * (p->W[b] > 1 ? p->W[b] - 1 : 1) * p->h[b];
+      eref[b] = e > 0 ? e : 1.0;
+    }
+    PECNN_HIP(hipMemcpyAsync(w.eref, eref.data(), sizeof(double) * p->n, hipMemcpyHostToDevice, st));
+    rc = reduce_launch(p, sim, s_cur, nullptr, w.now, w.part, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, *g, 1, fallback,
+                       w.active, stats_d, w.count);
+    PECNN_LAUNCH_CHECK("guard_kernel");
+    PECNN_HIP(hipMemcpyAsync(gc->host_count, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
+    PECNN_HIP(hipStreamSynchronize(st));
+  }
+
+  float* buf[3] = {s_prev, s_cur, w.X};
+  int k = 0;
+  const int chunk = guard_on ? g->check_every : n_steps;
+  while (k < n_steps) {
+    const int len = chunk < n_steps - k ? chunk : n_steps - k;
+    const bool with_ms = *gc->host_count > 0;
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.buf[0] = buf[0]; key.buf[1] = buf[1]; key.buf[2] = buf[2]; key.buf[3] = w.T;
+    key.len = len; key.with_ms = with_ms; key.guard = guard_on; key.ms_cfg = p->ms_cfg; key.cnn_cfg = p->cnn_cfg;
+    key.ch = m->ch; key.prec = m->precision; key.substeps = g->substeps; key.dt = m->dt; key.alpha = m->isru_alpha;
+    key.theta = m->theta; key.sim = *simp; key.gd = *g; key.fallback = fallback; key.ws = ws;
+    key.stats = stats_d;
+    hipGraphExec_t exec = nullptr;
+    for (auto& e : gc->entries)
+      if (e.key == key) { exec = e.exec; break; }
+    if (!exec) {
+      hipGraph_t graph;
+      PECNN_HIP(hipStreamBeginCapture(gc->capture, hipStreamCaptureModeThreadLocal));
+      rc = record_chunk(p, m, sim, g, buf, w.T, len, with_ms, guard_on, fallback, stats_d, w, gc->capture);
+      hipError_t e2 = hipStreamEndCapture(gc->capture, &graph);
+      if (rc) return rc;
+      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+      hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
+      if (gc->entries.size() >= 24) {
+        (void)hipGraphExecDestroy(gc->entries.front().exec);
+        gc->entries.erase(gc->entries.begin());
+      }
+      gc->entries.push_back(GraphEntry{key, exec});
+    }
+    PECNN_HIP(hipGraphLaunch(exec, st));
+    for (int i = 0; i < len; ++i) {
+      float* t = buf[0];
+      buf[0] = buf[1];
+      buf[1] = buf[2];
+      buf[2] = t;
+    }
+    k += len;
+    if (guard_on && k < n_steps) {
+      PECNN_HIP(hipMemcpyAsync(gc->host_count, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
+      PECNN_HIP(hipStreamSynchronize(st));
+    }
+  }
+  // hand the last two states back in the caller's buffers
+  if (buf[0] != s_prev || buf[1] != s_cur) {
+    if (buf[0] == s_cur) {  // (s_cur, X)
+      PECNN_HIP(hipMemcpyAsync(s_prev, s_cur, sb, hipMemcpyDeviceToDevice, st));
+      PECNN_HIP(hipMemcpyAsync(s_cur, w.X, sb, hipMemcpyDeviceToDevice, st));
+    } else {  // (X, s_prev)
+      PECNN_HIP(hipMemcpyAsync(s_cur, s_prev, sb, hipMemcpyDeviceToDevice, st));
+      PECNN_HIP(hipMemcpyAsync(s_prev, w.X, sb, hipMemcpyDeviceToDevice, st));
+    }
+  }
+  return PECNN_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+static int time_launches(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, float* out_ms,
+                         const std::function<int(int)>& launch) {
+  int rc = launch(0);  // warm-up
+  if (rc) return rc;
+  PECNN_HIP(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r)
+    if ((rc = launch(r))) return rc;
+  PECNN_HIP(hipEventRecord(e1, st));
+  PECNN_HIP(hipEventSynchronize(e1));
+  float t = 0.f;
+  PECNN_HIP(hipEventElapsedTime(&t, e0, e1));
+  *out_ms = t / reps;
+  return PECNN_OK;
+}
+
+static int autotune_impl(pecnn_plan* p, const cloth_ms_params* prm, const pecnn_model* m, float* s_a, float* s_b,
+                         float* s_c, int reps, float* ms_ms, float* cnn_ms, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1) {
+  const MsParamsDev P = ms_params_dev(prm);
+  float best = 1e30f;
+  int best_cfg = p->ms_cfg;
+  for (int c = 0; c < kNumMsCfg; ++c) {
+    float t = 0.f;
+    int rc = time_launches(st, e0, e1, reps, &t, [&](int r) {
+      return ms_step_once(p, c, P, (r & 1) ? s_b : s_a, (r & 1) ? s_a : s_b, nullptr, st);
+    });
+    if (rc) return rc;
+    if (ms_ms) ms_ms[c] = t;
+    if (t < best) { best = t; best_cfg = c; }
+  }
+  p->ms_cfg = best_cfg;
+  if (!m) return PECNN_OK;
+  best = 1e30f;
+  best_cfg = p->cnn_cfg;
+  float* bs[3] = {s_a, s_b, s_c};
+  for (int c = 0; c < kNumCnnCfg; ++c) {
+    float t = 0.f;
+    int rc = time_launches(st, e0, e1, reps, &t, [&](int r) {
+      return cnn_forward_launch(p, c, m, bs[r % 3], bs[(r + 1) % 3], bs[(r + 2) % 3], nullptr, st);
+    });
+    if (rc) return rc;
+    if (cnn_ms) cnn_ms[c] = t;
+    if (t < best) { best = t; best_cfg = c; }
+  }
+  p->cnn_cfg = best_cfg;
+  return PECNN_OK;
+}
+
+int pecnn_autotune(pecnn_plan* p, const cloth_ms_params* prm, const pecnn_model* m, float* s_a, float* s_b,
+                   float* s_c, int32_t reps, float* ms_ms, float* cnn_ms, void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((rc = check_ms_params(prm))) return rc;
+  if (m && (rc = check_model(m))) return rc;
+  if (!s_a || !s_b || !s_c || reps < 1) { set_error("null scratch state or reps < 1"); return PECNN_E_INVALID; }
+  hipEvent_t e0, e1;
+  PECNN_HIP(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  rc = autotune_impl(p, prm, m, s_a, s_b, s_c, reps, ms_ms, cnn_ms, (hipStream_t)stream, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // extern "C"

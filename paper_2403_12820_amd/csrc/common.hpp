@@ -1,0 +1,118 @@
+// Shared device/host definitions of the pecnn HIP library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/pecnn.h"
+
+namespace pecnn {
+
+// ----------------------------------------------------------------- per-instance record
+// One record per cloth instance, kept in the plan's device memory.
+struct InstDev {
+  int32_t H, W;    // rows, columns
+  int64_t off;     // first node of the instance in the batch planes
+  float h, mass;   // rest spacing, node mass
+  float ax, ay, az;  // constant external (wind) acceleration
+  int32_t pad;
+};
+static_assert(sizeof(InstDev) == 40, "InstDev layout");
+
+// Tile shapes. Each config has its own per-instance tile prefix in the plan.
+// Mass-spring step: TX x TY nodes per workgroup, each thread RY nodes along y.
+struct MsCfg { int tx, ty, ry; };
+constexpr int kNumMsCfg = 5;
+constexpr MsCfg kMsCfg[kNumMsCfg] = {{32, 8, 1}, {64, 4, 1}, {16, 16, 1}, {32, 16, 2}, {64, 8, 2}};
+// CNN cell: TX x TY nodes per workgroup of 4 waves; TX is a multiple of 16 (one MFMA column block).
+struct CnnCfg { int tx, ty; };
+constexpr int kNumCnnCfg = 3;
+constexpr CnnCfg kCnnCfg[kNumCnnCfg] = {{64, 4}, {32, 8}, {16, 16}};
+// Node-parallel kernels (reductions, backward): flat chunks of kChunk nodes per instance.
+constexpr int kChunk = 256;
+constexpr int kNumCfg = kNumMsCfg + kNumCnnCfg + 1;
+constexpr int kCfgChunk = kNumMsCfg + kNumCnnCfg;
+inline int ms_cfg_slot(int c) { return c; }
+inline int cnn_cfg_slot(int c) { return kNumMsCfg + c; }
+
+inline __host__ __device__ int tiles_of(int H, int W, int tx, int ty) {
+  return ((H + ty - 1) / ty) * ((W + tx - 1) / tx);
+}
+
+// ----------------------------------------------------------------- tile scheduling
+// Find the instance owning global tile t: largest b with prefix[b] <= t (prefix[0] = 0).
+__device__ __forceinline__ int find_instance(const int32_t* __restrict__ prefix, int n, int t) {
+  int lo = 0, hi = n;  // invariant: prefix[lo] <= t < prefix[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give each XCD a
+// contiguous range of tiles so that neighbouring tiles, which share halo rows, hit the same L2.
+// Returns the first tile of this workgroup and the stride between its tiles.
+__device__ __forceinline__ void xcd_tile_range(int n_tiles, int& first, int& stride, int& count) {
+  const int G = gridDim.x;
+  const int w = blockIdx.x;
+  const int xcd = w & 7;
+  const int groups = (G + 7) >> 3;          // workgroups per XCD (upper bound)
+  const int slot = w >> 3;                  // index of this workgroup within its XCD
+  const int per_xcd = (n_tiles + 7) >> 3;   // tiles per XCD
+  const int base = xcd * per_xcd;
+  const int end = min(n_tiles, base + per_xcd);
+  // workgroups on this XCD: those w with w % 8 == xcd, w < G
+  const int wg_here = (G - xcd + 7) >> 3;
+  (void)groups;
+  first = base + slot;
+  stride = wg_here;
+  count = (first < end) ? (end - first + stride - 1) / stride : 0;
+}
+
+struct MsParamsDev {
+  float k[3];     // spring constants per family
+  float mu, drag;
+  float g[3];
+  float dt;
+};
+
+// ----------------------------------------------------------------- plan
+}  // namespace pecnn
+
+struct pecnn_plan {
+  int32_t n;
+  int64_t total;
+  int32_t* H;        // host copies
+  int32_t* W;
+  int64_t* off;
+  float* h;
+  float* mass;
+  float* a_ext;
+  const uint8_t* pin;                   // device, caller-owned
+  pecnn::InstDev* d_inst;               // device, inside the caller's plan memory
+  int32_t* d_prefix[pecnn::kNumCfg];    // device prefix of tiles per instance, per config
+  int32_t n_tiles[pecnn::kNumCfg];
+  int32_t ms_cfg;                       // chosen configs (autotuner or defaults)
+  int32_t cnn_cfg;
+  int32_t max_hw;                       // largest H*W of an instance
+  void* graph_cache;                    // rollout graph cache (host object)
+};
+
+namespace pecnn {
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int num_cus();
+}  // namespace pecnn
+
+#define PECNN_HIP(call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return pecnn::hip_fail(e_, #call); \
+  } while (0)
+
+#define PECNN_LAUNCH_CHECK(what)                          \
+  do {                                                    \
+    hipError_t e_ = hipGetLastError();                    \
+    if (e_ != hipSuccess) return pecnn::hip_fail(e_, what); \
+  } while (0)

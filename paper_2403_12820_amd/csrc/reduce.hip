@@ -1,0 +1,231 @@
+// FP64 diagnostics (position error, energy, stretch ratio), the data term of the loss (eq. 8),
+// Adam (Table 1) and the training-window gather. Reductions are two-stage with a fixed order
+// (per-chunk tree in LDS, then per-instance or global sums in index order): bitwise
+// reproducible run to run.
+#include "common.hpp"
+
+namespace pecnn {
+
+// forward half of the 12 springs, so that each spring is counted once
+struct HalfSpring { int dy, dx, fam; };
+__device__ constexpr HalfSpring kHalf[6] = {{0, 1, 0}, {1, 0, 0}, {1, 1, 1}, {1, -1, 1}, {0, 2, 2}, {2, 0, 2}};
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void reduce_chunk_kernel(
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int64_t N,
+    const float* __restrict__ s, const float* __restrict__ s_ref, MsParamsDev P, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int t = blockIdx.x;
+  const int b = find_instance(prefix, n_inst, t);
+  const InstDev I = inst[b];
+  const int64_t local = (int64_t)(t - prefix[b]) * kChunk + threadIdx.x;
+  double e2 = 0.0, en = 0.0, st_s = 0.0, st_a = 0.0;
+  if (local < (int64_t)I.H * I.W) {
+    const int i = (int)(local / I.W), j = (int)(local % I.W);
+    const int64_t p = I.off + local;
+    const double m = I.mass;
+    const double ge[3] = {(double)P.g[0] + I.ax, (double)P.g[1] + I.ay, (double)P.g[2] + I.az};
+    double x[3];
+    for (int a = 0; a < 3; ++a) {
+      x[a] = s[a * N + p];
+      const double v = s[(3 + a) * N + p];
+      en += 0.5 * m * v * v - m * ge[a] * x[a];
+      if (s_ref) {
+        const double d = x[a] - (double)s_ref[a * N + p];
+        e2 += d * d;
+      }
+    }
+    const double h = I.h;
+    const double L[3] = {h, 1.4142135623730951 * h, 2.0 * h};
+    for (int q = 0; q < 6; ++q) {
+      const int ii = i + kHalf[q].dy, jj = j + kHalf[q].dx;
+      // structural springs pointing backwards are visited by the other end; stretch needs all
+      if (ii < 0 || ii >= I.H || jj < 0 || jj >= I.W) continue;
+      const int64_t pj = I.off + (int64_t)ii * I.W + jj;
+      double d2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        const double d = x[a] - (double)s[a * N + pj];
+        d2 += d * d;
+      }
+      const double r = sqrt(d2);
+      const int f = kHalf[q].fam;
+      const double dr = r - L[f];
+      en += 0.5 * (double)P.k[f] * dr * dr;
+      const double ratio = r / L[f];
+      if (f == 0) st_s = fmax(st_s, ratio);
+      st_a = fmax(st_a, ratio);
+    }
+  }
+  e2 = block_sum(e2, sh);
+  en = block_sum(en, sh);
+  st_s = block_max(st_s, sh);
+  st_a = block_max(st_a, sh);
+  if (threadIdx.x == 0) {
+    partial[4 * t + 0] = e2;
+    partial[4 * t + 1] = en;
+    partial[4 * t + 2] = st_s;
+    partial[4 * t + 3] = st_a;
+  }
+}
+
+__global__ void reduce_final_kernel(const int32_t* __restrict__ prefix, int n_inst, const double* __restrict__ partial,
+                                    double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_inst) return;
+  double e2 = 0.0, en = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int t = prefix[b]; t < prefix[b + 1]; ++t) {
+    e2 += partial[4 * t + 0];
+    en += partial[4 * t + 1];
+    s1 = fmax(s1, partial[4 * t + 2]);
+    s2 = fmax(s2, partial[4 * t + 3]);
+  }
+  out[4 * b + 0] = e2;
+  out[4 * b + 1] = en;
+  out[4 * b + 2] = s1;
+  out[4 * b + 3] = s2;
+}
+
+size_t reduce_ws_bytes(const pecnn_plan* plan) {
+  return (size_t)plan->n_tiles[kCfgChunk] * 4 * sizeof(double) + 256;
+}
+
+int reduce_launch(const pecnn_plan* plan, const MsParamsDev& P, const float* s, const float* s_ref, double* out,
+                  void* ws, hipStream_t st) {
+  const int nt = plan->n_tiles[kCfgChunk];
+  double* partial = (double*)ws;
+  hipLaunchKernelGGL(reduce_chunk_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk],
+                     plan->n, plan->total, s, s_ref, P, partial);
+  PECNN_LAUNCH_CHECK("reduce_chunk_kernel");
+  hipLaunchKernelGGL(reduce_final_kernel, dim3((plan->n + 255) / 256), dim3(256), 0, st, plan->d_prefix[kCfgChunk],
+                     plan->n, partial, out);
+  PECNN_LAUNCH_CHECK("reduce_final_kernel");
+  return PECNN_OK;
+}
+
+// ---------------------------------------------------------------- loss (eq. 8, data term)
+__global__ __launch_bounds__(256) void loss_chunk_kernel(
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int64_t N,
+    const uint8_t* __restrict__ pin, const float* __restrict__ sh_, const float* __restrict__ st_, float isx2,
+    float isv2, float gscale, double* __restrict__ partial, float* __restrict__ g) {
+  __shared__ double sh[256];
+  const int t = blockIdx.x;
+  const int b = find_instance(prefix, n_inst, t);
+  const InstDev I = inst[b];
+  const int64_t local = (int64_t)(t - prefix[b]) * kChunk + threadIdx.x;
+  double acc = 0.0;
+  if (local < (int64_t)I.H * I.W) {
+    const int64_t p = I.off + local;
+    if (!pin[p]) {
+      for (int c = 0; c < 6; ++c) {
+        const float d = sh_[c * N + p] - st_[c * N + p];
+        const float is2 = c < 3 ? isx2 : isv2;
+        acc += (double)d * (double)d * (double)is2;
+        if (g) g[c * N + p] += gscale * d * is2;
+      }
+    }
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[t] = acc;
+}
+
+__global__ __launch_bounds__(256) void loss_final_kernel(const double* __restrict__ partial, int n, double scale,
+                                                          double* __restrict__ loss) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256) s += partial[t];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *loss += scale * s;
+}
+
+int loss_launch(const pecnn_plan* plan, const float* s_hat, const float* s_true, float sx, float sv, float w,
+                int64_t n_free, double* loss, float* g, void* ws, hipStream_t st) {
+  const int nt = plan->n_tiles[kCfgChunk];
+  double* partial = (double*)ws;
+  const float isx2 = 1.f / (sx * sx), isv2 = 1.f / (sv * sv);
+  const float gscale = (float)(2.0 * (double)w / (double)n_free);
+  hipLaunchKernelGGL(loss_chunk_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk], plan->n,
+                     plan->total, plan->pin, s_hat, s_true, isx2, isv2, gscale, partial, g);
+  PECNN_LAUNCH_CHECK("loss_chunk_kernel");
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, partial, nt, (double)w / (double)n_free, loss);
+  PECNN_LAUNCH_CHECK("loss_final_kernel");
+  return PECNN_OK;
+}
+
+// ---------------------------------------------------------------- Adam
+__global__ void adam_kernel(int64_t n, float lr, float b1, float b2, float eps, float ibc1, float ibc2,
+                            float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi * ibc1) / (sqrtf(vi * ibc2) + eps);
+}
+
+int adam_launch(int64_t n, float lr, float b1, float b2, float eps, int t, float* th, float* m, float* v,
+                const float* g, hipStream_t st) {
+  const double bc1 = 1.0 - pow((double)b1, t), bc2 = 1.0 - pow((double)b2, t);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lr, b1, b2, eps,
+                     (float)(1.0 / bc1), (float)(1.0 / bc2), th, m, v, g);
+  PECNN_LAUNCH_CHECK("adam_kernel");
+  return PECNN_OK;
+}
+
+// ---------------------------------------------------------------- training windows
+__global__ void gather_kernel(const float* __restrict__ traj, int64_t traj_nodes, int n_saved,
+                              const int64_t* __restrict__ traj_off, int n_traj, const int32_t* __restrict__ traj_inst,
+                              const int32_t* __restrict__ frame_idx, int n_win, int npw, int n_frames,
+                              float* __restrict__ out) {
+  const int w = blockIdx.y;
+  const int tc = blockIdx.z;  // frame * 6 + channel
+  const int t = tc / 6, c = tc % 6;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= npw) return;
+  int f = frame_idx[w] + t;
+  f = f < 0 ? 0 : (f >= n_saved ? n_saved - 1 : f);
+  int b = traj_inst[w];
+  b = b < 0 ? 0 : (b >= n_traj ? n_traj - 1 : b);
+  const int64_t lo = traj_off[b], hi = traj_off[b + 1];
+  const int64_t tot = (int64_t)n_win * npw;
+  float v = 0.f;
+  if (lo + node < hi && hi <= traj_nodes) v = traj[((int64_t)f * 6 + c) * traj_nodes + lo + node];
+  out[((int64_t)t * 6 + c) * tot + (int64_t)w * npw + node] = v;
+}
+
+int gather_launch(const float* traj, int64_t traj_nodes, int n_saved, const int64_t* traj_off, int n_traj,
+                  const int32_t* traj_inst, const int32_t* frame_idx, int n_win, int npw, int n_frames,
+                  float* out, hipStream_t st) {
+  dim3 grid((npw + 255) / 256, n_win, n_frames * 6);
+  hipLaunchKernelGGL(gather_kernel, grid, dim3(256), 0, st, traj, traj_nodes, n_saved, traj_off, n_traj, traj_inst,
+                     frame_idx, n_win, npw, n_frames, out);
+  PECNN_LAUNCH_CHECK("gather_kernel");
+  return PECNN_OK;
+}
+
+}  // namespace pecnn

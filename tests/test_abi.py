@@ -1,0 +1,72 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/pecnn.h declares, and rejects invalid arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2403_12820_amd import _lib as L
+from paper_2403_12820_amd import inputs as I
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pecnn.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\**\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declarations_are_exported():
+    names = _declared()
+    assert "cloth_ms_step" in names and "pecnn_forward" in names and "pecnn_backward" in names
+    assert "pecnn_rollout" in names
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.exported_symbols()) == names
+
+
+def test_theta_size_matches_layout():
+    for ch in (16, 32):
+        assert L.pecnn_theta_size(ch) == I.theta_size(ch)
+    assert L.lib().pecnn_theta_size(0) == -1
+
+
+def test_status_strings():
+    lib = L.lib()
+    for rc in (0, -1, -2, -3, -4, -5):
+        assert lib.pecnn_status_string(rc)
+    assert lib.pecnn_status_string(-99) == b"unknown status"
+
+
+def _desc(H, W, h=0.1, m=0.01):
+    n = len(H)
+    arrs = [np.array(H, np.int32), np.array(W, np.int32), np.full(n, h, np.float32), np.full(n, m, np.float32),
+            np.zeros(3 * n, np.float32)]
+    d = L.BatchDesc(n, *[a.ctypes.data for a in arrs])
+    return d, arrs
+
+
+def test_plan_bytes_and_shape_validation():
+    lib = L.lib()
+    nb = C.c_size_t(0)
+    d, keep = _desc([32, 1], [32, 2])
+    assert lib.pecnn_plan_device_bytes(C.byref(d), C.byref(nb)) == 0 and nb.value > 0
+    for H, W in (([1], [1]), ([0], [5]), ([5], [-1]), ([1 << 12], [1 << 12])):
+        d, keep = _desc(H, W)
+        assert lib.pecnn_plan_device_bytes(C.byref(d), C.byref(nb)) == -2
+    d, keep = _desc([4], [4], h=-1.0)
+    assert lib.pecnn_plan_device_bytes(C.byref(d), C.byref(nb)) == -1
+    assert b"spacing" in lib.pecnn_last_error()
+
+
+def test_null_arguments_rejected_without_device():
+    lib = L.lib()
+    p = L.ms_params(I.Material())
+    assert lib.cloth_ms_step(None, C.byref(p), None, None, 1, None, None, 0, None) == -1
+    assert lib.pecnn_forward(None, None, None, None, None, None) == -1
+    assert lib.pecnn_adam_step(0, 1e-3, 0.9, 0.999, 1e-8, 1, None, None, None, None, None) == -1
+    assert lib.pecnn_gather_windows(None, 1, 1, None, 1, None, None, 1, 1, 1, None, None) == -1

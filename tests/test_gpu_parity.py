@@ -1,0 +1,335 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (derived in the design notes):
+  * mass-spring step, FP32: positions within 1e-5 of the cloth width; velocities within
+    max(1e-5 |v|_inf, the worst-case FP32 rounding floor of the spring lengths);
+  * CNN frame, FP32 operands: 1e-5 relative (inf-norm) on the new state and on dv;
+  * CNN frame, bf16 operands: 1e-2 relative on dv against the exact FP64 oracle, and close to
+    the emulated-bf16 oracle (same operand rounding, FP64 accumulation);
+  * backward: 1e-4 relative on every gradient (FP32 accumulation over up to 4k terms);
+  * FP64 reductions: 1e-12 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_12820_amd import inputs as I
+from tests.gpu_util import dev_tensor, perturbed_batch, ragged_sizes, ms_velocity_floor, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+MAT = I.Material()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2403_12820_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _ms_gpu(L, torch, batch, s, n_steps=1, cfg=None, mat=MAT, active=None):
+    plan = L.Plan.from_batch(batch)
+    if cfg is not None:
+        plan.set_tiles(ms_cfg=cfg)
+    a = dev_tensor(s)
+    out = torch.zeros_like(a)
+    L.cloth_ms_step(plan, L.ms_params(mat), a, out, n_steps, active=active)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+# ------------------------------------------------------------------ mass-spring step
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+def test_ms_step_matches_oracle(torch_mod, L, cfg):
+    sizes = ragged_sizes() + [(32, 32)]
+    batch = perturbed_batch(sizes, seed=100)
+    got = _ms_gpu(L, torch_mod, batch, batch.state, 1, cfg)
+    ref = oracle.batch_ms_step(batch, batch.state, MAT, 1)
+    width = max((w - 1) * h for w, h in zip(batch.W, batch.h))
+    assert np.abs(got[:3] - ref[:3]).max() <= 1e-5 * width
+    tol_v = max(1e-5 * np.abs(ref[3:]).max(), ms_velocity_floor(batch, MAT))
+    assert np.abs(got[3:] - ref[3:]).max() <= tol_v, (np.abs(got[3:] - ref[3:]).max(), tol_v)
+
+
+def test_ms_tile_configs_bitwise_equal(torch_mod, L):
+    batch = perturbed_batch(ragged_sizes(), seed=101)
+    outs = [_ms_gpu(L, torch_mod, batch, batch.state, 3, cfg) for cfg in range(5)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_ms_config0_rollout_400_steps(torch_mod, L):
+    """32 x 32, two top corners, z-noise seed 0, dt = 5e-4, 400 steps (0.2 s) against the oracle."""
+    sc = I.make_scene(32, 32, "two_top_corners", noise_sigma=1e-3, seed=0)
+    batch = I.make_batch([sc])
+    got = _ms_gpu(L, torch_mod, batch, batch.state, 400)
+    ref = oracle.batch_ms_step(batch, batch.state, MAT, 400)
+    width = 31 * sc.h
+    err_x = np.abs(got[:3] - ref[:3]).max() / width
+    assert err_x <= 1e-5, err_x
+    assert rel_inf(got[3:], ref[3:]) <= 1e-3
+
+
+def test_ms_active_mask_skips_instances(torch_mod, L):
+    torch = torch_mod
+    batch = perturbed_batch([(9, 9), (16, 40), (3, 3)], seed=102)
+    act = torch.tensor([1, 0, 1], dtype=torch.uint8, device="cuda")
+    plan = L.Plan.from_batch(batch)
+    a = dev_tensor(batch.state)
+    out = torch.full_like(a, 7.0)
+    L.cloth_ms_step(plan, L.ms_params(MAT), a, out, 2, active=act)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    sl = batch.instance(1)
+    assert np.all(o[:, sl] == 7.0)
+    ref = oracle.batch_ms_step(batch, batch.state, MAT, 2)
+    for b in (0, 2):
+        s = batch.instance(b)
+        assert np.abs(o[:3, s] - ref[:3, s]).max() < 1e-5
+
+
+def test_ms_single_spring_closed_form_gpu(torch_mod, L):
+    """P2 on the GPU: 1 x 2 grid, node 0 pinned, u_n = u0 [cos n th - a/(2 sin th) sin n th]."""
+    u0, n, k, m, dt = 1e-3, 200, 1000.0, 1.0 / 1024, 5e-4
+    mat = I.Material(k_struct=k, mu=0.0, drag=0.0, g=(0.0, 0.0, 0.0), dt=dt)
+    sc = I.make_scene(1, 2, "one_top_corner", noise_sigma=0.0)
+    sc.state[0, 1] += u0
+    batch = I.make_batch([sc])
+    got = _ms_gpu(L, torch_mod, batch, batch.state, n, mat=mat)
+    a = k / m * dt * dt
+    th = math.acos(1 - a / 2)
+    ref = u0 * (math.cos(n * th) - a / (2 * math.sin(th)) * math.sin(n * th))
+    u = got[0, 1] - np.float32(sc.state[0, 1] - u0)
+    assert abs(u - ref) < 1e-4 * u0 + 2e-7, (u, ref)
+
+
+def test_ms_rest_and_free_fall_gpu(torch_mod, L):
+    mat = I.Material(g=(0.0, 0.0, 0.0))
+    sc = I.make_scene(20, 30, "two_top_corners", noise_sigma=0.0)
+    batch = I.make_batch([sc])
+    got = _ms_gpu(L, torch_mod, batch, batch.state, 50, mat=mat)
+    X = np.abs(sc.state[:3]).max()
+    assert np.abs(got[:3] - sc.state[:3]).max() <= 1e-6 * max(1.0, X)
+    sc2 = I.make_scene(9, 9, "none", noise_sigma=0.0)
+    batch2 = I.make_batch([sc2])
+    n = 40
+    got = _ms_gpu(L, torch_mod, batch2, batch2.state, n)
+    g = np.array(MAT.g)
+    assert np.abs(got[5] - n * g[2] * MAT.dt).max() < 1e-5 * abs(n * g[2] * MAT.dt) + 1e-6
+
+
+# ------------------------------------------------------------------ CNN forward
+def _cnn_inputs(sizes, seed, ch, scale):
+    batch = perturbed_batch(sizes, seed=seed, vel=0.1)
+    s1 = batch.state.astype(np.float64)
+    s0 = s1.copy()
+    s0[3:] -= I.random_array((3, batch.total), seed=seed + 21, scale=0.05)
+    s0[:3] -= 5e-3 * s1[3:]
+    th = (I.init_theta(ch, seed=seed + 22).astype(np.float64) * scale).astype(np.float32)
+    return batch, s0.astype(np.float32), s1.astype(np.float32), th
+
+
+def _cnn_gpu(L, torch, batch, s0, s1, th, ch, prec, dt=5e-3, cfg=None):
+    plan = L.Plan.from_batch(batch)
+    if cfg is not None:
+        plan.set_tiles(cnn_cfg=cfg)
+    t = dev_tensor(th)
+    model = L.make_model(t, ch, prec, dt=dt)
+    a, b = dev_tensor(s0), dev_tensor(s1)
+    out = torch.zeros_like(b)
+    L.pecnn_forward(plan, model, a, b, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _dv_from_state(batch, s1, out, dt):
+    """v' - v - dt a for free nodes (the network output); pinned nodes give 0."""
+    a = np.repeat(batch.a_ext.astype(np.float64), np.diff(batch.node_off), axis=0).T
+    dv = out[3:] - s1[3:].astype(np.float64) - dt * a
+    dv[:, batch.pin == 1] = 0.0
+    return dv
+
+
+@pytest.mark.parametrize("ch", [16, 32])
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+def test_cnn_forward_fp32_matches_oracle(torch_mod, L, ch, cfg):
+    batch, s0, s1, th = _cnn_inputs(ragged_sizes(), 200 + ch, ch, 30.0)
+    got = _cnn_gpu(L, torch_mod, batch, s0, s1, th, ch, L.PECNN_FP32, cfg=cfg)
+    ref, dv_ref = oracle.batch_cnn_forward(batch, ch, 1.0, 5e-3, th.astype(np.float64), s0, s1)
+    assert rel_inf(got[3:], ref[3:]) <= 1e-5
+    assert rel_inf(got[:3], ref[:3]) <= 1e-6
+    dv = _dv_from_state(batch, s1, got, 5e-3)
+    dv_ref[:, batch.pin == 1] = 0.0
+    assert rel_inf(dv, dv_ref) <= 1e-5, rel_inf(dv, dv_ref)
+
+
+@pytest.mark.parametrize("ch", [16, 32])
+def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch):
+    batch, s0, s1, th = _cnn_inputs(ragged_sizes(), 300 + ch, ch, 30.0)
+    got = _cnn_gpu(L, torch_mod, batch, s0, s1, th, ch, L.PECNN_BF16)
+    _, dv_exact = oracle.batch_cnn_forward(batch, ch, 1.0, 5e-3, th.astype(np.float64), s0, s1)
+    _, dv_emu = oracle.batch_cnn_forward(batch, ch, 1.0, 5e-3, th.astype(np.float64), s0, s1, emu=7)
+    for d in (dv_exact, dv_emu):
+        d[:, batch.pin == 1] = 0.0
+    dv = _dv_from_state(batch, s1, got, 5e-3)
+    e_exact = rel_inf(dv, dv_exact)
+    e_emu = rel_inf(dv, dv_emu)
+    assert e_exact <= 1e-2, e_exact
+    # same operand rounding: only FP32 accumulation order and rare bf16 rounding flips of
+    # intermediate features differ; the typical node agrees to FP32 accumulation accuracy
+    assert e_emu <= 2e-3, e_emu
+    med = np.median(np.abs(dv - dv_emu)) / np.abs(dv_emu).max()
+    assert med <= 1e-5, med
+
+
+def test_cnn_tile_configs_bitwise_equal(torch_mod, L):
+    for prec in (0, 1):
+        batch, s0, s1, th = _cnn_inputs(ragged_sizes(), 400, 32, 10.0)
+        outs = [_cnn_gpu(L, torch_mod, batch, s0, s1, th, 32, prec, cfg=c) for c in range(3)]
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+
+
+def test_cnn_config0_rollout_100_steps(torch_mod, L):
+    """32 x 32 scene of the plain-method configuration, Ch = 16, theta ~ N(0, 0.02) seed 1,
+    S^{-1} = S^0, dt = 1e-3, 100 FP32 frames against the oracle."""
+    torch = torch_mod
+    sc = I.make_scene(32, 32, "two_top_corners", noise_sigma=1e-3, seed=0)
+    batch = I.make_batch([sc])
+    th = I.init_theta(16, seed=1)
+    plan = L.Plan.from_batch(batch)
+    t = dev_tensor(th)
+    model = L.make_model(t, 16, L.PECNN_FP32, dt=1e-3)
+    bufs = [dev_tensor(sc.state), dev_tensor(sc.state), torch.zeros(6, 1024, device="cuda")]
+    for k in range(100):
+        L.pecnn_forward(plan, model, bufs[0], bufs[1], bufs[2])
+        bufs = [bufs[1], bufs[2], bufs[0]]
+    torch.cuda.synchronize()
+    got = bufs[1].cpu().numpy().astype(np.float64)
+    sp = sc.state.astype(np.float64)
+    sk = sp.copy()
+    for k in range(100):
+        sn, _ = oracle.cnn_forward(32, 32, 16, 1.0, 1e-3, sc.a_ext, sc.pin, th.astype(np.float64), sp, sk)
+        sp, sk = sk, sn
+    assert np.abs(got[:3] - sk[:3]).max() <= 1e-5 * 31 * sc.h
+    assert rel_inf(got[3:], sk[3:]) <= 1e-5
+
+
+# ------------------------------------------------------------------ backward, loss, Adam
+@pytest.mark.parametrize("ch", [16, 32])
+def test_backward_matches_oracle(torch_mod, L, ch):
+    torch = torch_mod
+    batch, s0, s1, th = _cnn_inputs([(8, 8), (17, 23), (1, 2), (5, 3)], 500 + ch, ch, 20.0)
+    gn = I.random_array((6, batch.total), seed=510).astype(np.float32)
+    plan = L.Plan.from_batch(batch)
+    t = dev_tensor(th)
+    model = L.make_model(t, ch, L.PECNN_FP32, dt=5e-3)
+    a, b, g = dev_tensor(s0), dev_tensor(s1), dev_tensor(gn)
+    gc = torch.zeros_like(a)
+    gp = torch.zeros_like(a)
+    gt = torch.zeros(th.size, device="cuda")
+    L.pecnn_backward(plan, model, a, b, g, gc, gp, gt)
+    torch.cuda.synchronize()
+    rc, rp, rt = oracle.batch_cnn_backward(batch, ch, 1.0, 5e-3, th.astype(np.float64), s0.astype(np.float64),
+                                           s1.astype(np.float64), gn.astype(np.float64))
+    assert rel_inf(gc.cpu().numpy(), rc) <= 1e-4
+    assert rel_inf(gp.cpu().numpy(), rp) <= 1e-4
+    assert rel_inf(gt.cpu().numpy(), rt) <= 1e-4
+    # accumulation semantics: a second call adds the same amount
+    L.pecnn_backward(plan, model, a, b, g, gc, gp, gt)
+    torch.cuda.synchronize()
+    assert rel_inf(gt.cpu().numpy(), 2 * rt) <= 1e-4
+
+
+def test_backward_is_deterministic(torch_mod, L):
+    torch = torch_mod
+    batch, s0, s1, th = _cnn_inputs([(40, 40), (13, 77)], 600, 32, 10.0)
+    gn = I.random_array((6, batch.total), seed=610).astype(np.float32)
+    plan = L.Plan.from_batch(batch)
+    t = dev_tensor(th)
+    model = L.make_model(t, 32, L.PECNN_FP32, dt=5e-3)
+    a, b, g = dev_tensor(s0), dev_tensor(s1), dev_tensor(gn)
+    res = []
+    for _ in range(2):
+        gt = torch.zeros(th.size, device="cuda")
+        gc = torch.zeros_like(a)
+        L.pecnn_backward(plan, model, a, b, g, gc, None, gt)
+        torch.cuda.synchronize()
+        res.append((gt.cpu().numpy(), gc.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_loss_and_adam_match_oracle(torch_mod, L):
+    torch = torch_mod
+    batch = perturbed_batch([(8, 8), (30, 20)], seed=700)
+    sh = batch.state.astype(np.float64) + I.random_array((6, batch.total), seed=701, scale=1e-2)
+    sh = sh.astype(np.float32)
+    n_free = int((batch.pin == 0).sum())
+    plan = L.Plan.from_batch(batch)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = torch.zeros(6, batch.total, device="cuda")
+    L.pecnn_loss_mse(plan, dev_tensor(sh), dev_tensor(batch.state), 0.01, 0.2, 0.75, n_free, loss, g)
+    torch.cuda.synchronize()
+    rv, rg = oracle.loss_mse(batch.pin, n_free, 0.01, 0.2, 0.75, sh, batch.state)
+    assert abs(loss.item() - rv) <= 1e-6 * abs(rv)
+    assert rel_inf(g.cpu().numpy(), rg) <= 1e-5
+    n = 4067
+    th0 = I.random_array((n,), seed=702).astype(np.float32)
+    gr = I.random_array((n,), seed=703).astype(np.float32)
+    th, m, v = dev_tensor(th0), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    rth, rm, rv2 = th0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 4):
+        L.pecnn_adam_step(th, m, v, dev_tensor(gr * t), t)
+        rth, rm, rv2 = oracle.adam(rth, rm, rv2, gr * t, t)
+    torch.cuda.synchronize()
+    assert np.abs(th.cpu().numpy() - rth).max() <= 1e-6
+
+
+def test_reduce_fp64_matches_oracle(torch_mod, L):
+    torch = torch_mod
+    batch = perturbed_batch(ragged_sizes(), seed=800)
+    ref_state = batch.state + I.random_array(batch.state.shape, seed=801, scale=1e-3).astype(np.float32)
+    plan = L.Plan.from_batch(batch)
+    out = torch.zeros(4 * batch.n, dtype=torch.float64, device="cuda")
+    L.cloth_reduce_fp64(plan, L.ms_params(MAT), dev_tensor(batch.state), dev_tensor(ref_state), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().reshape(-1, 4)
+    for b in range(batch.n):
+        H, W = int(batch.H[b]), int(batch.W[b])
+        sl = batch.instance(b)
+        s, r = batch.state[:, sl].astype(np.float64), ref_state[:, sl].astype(np.float64)
+        h, m = float(batch.h[b]), float(batch.mass[b])
+        a = batch.a_ext[b].astype(np.float64)
+        assert abs(o[b, 0] - oracle.sq_pos_err(H, W, s, r)) <= 1e-12 * max(1e-30, oracle.sq_pos_err(H, W, s, r))
+        e = oracle.energy(H, W, h, m, a, s, MAT)
+        assert abs(o[b, 1] - e) <= 1e-10 * max(1.0, abs(e))
+        assert abs(o[b, 2] - oracle.max_stretch(H, W, h, s, 1)) <= 1e-12
+        assert abs(o[b, 3] - oracle.max_stretch(H, W, h, s, 7)) <= 1e-12
+
+
+def test_gather_windows(torch_mod, L):
+    torch = torch_mod
+    n_traj, F, npw = 3, 12, 64
+    off = np.arange(n_traj + 1, dtype=np.int64) * npw
+    traj = I.random_array((F, 6, n_traj * npw), seed=900).astype(np.float32)
+    inst = np.array([2, 0, 1, 2], np.int32)
+    fr = np.array([0, 5, 3, 2], np.int32)
+    out = torch.zeros(4, 6, 4 * npw, device="cuda")
+    L.pecnn_gather_windows(dev_tensor(traj), n_traj * npw, F, dev_tensor(off), n_traj, dev_tensor(inst),
+                           dev_tensor(fr), 4, npw, 4, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for w in range(4):
+        for t in range(4):
+            np.testing.assert_array_equal(o[t, :, w * npw:(w + 1) * npw],
+                                          traj[fr[w] + t, :, inst[w] * npw:(inst[w] + 1) * npw])
