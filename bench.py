@@ -1,0 +1,222 @@
+"""Benchmark: cloth node-steps/s of the bf16 CNN rollout against the FP32 mass-spring step.
+
+One bench step = one network frame of the whole batch through pecnn_rollout (bf16 convolutions
+on the matrix cores, FP32 state; guard with FP64 energy/stretch reductions every 10 frames,
+run as hipGraph-captured chunks). Inputs are synthetic and resident in HBM before timing.
+
+Printed (one JSON line): the contract fields, plus
+  roofline      - the dominant kernel (the CNN frame) timed alone with HIP events on its stream:
+                  algorithmic bytes per launch / mean launch time, against 8 TB/s HBM;
+                  traffic (measured HBM bytes per launch) from the committed rocprofv3 counter
+                  summary when it was taken on the current kernel source, else null;
+  cpu_baseline  - the FP64 oracle's CNN frame on a bounded sample, single thread;
+  config        - the workload plus the FP32 mass-spring throughput on the same batch and the
+                  sim-equivalent rate (one frame covers 'stride' mass-spring steps).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cloth node-steps/s: BF16 CNN rollout vs FP32 mass-spring, at fixed RMS error"
+HBM_PEAK_GBS = 8000.0
+CNN_BYTES_PER_NODE = 73  # read S^k and S^{k-1} (24 B each), write S^{k+1} (24 B), pin flag (1 B)
+MS_BYTES_PER_NODE = 49   # read S (24 B), write S' (24 B), pin flag (1 B)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cnn_fwd_bf16.json")
+WEIGHTS = os.path.join(ROOT, "paper_2403_12820_amd", "weights", "pecnn_ch32.npy")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("cnn_fwd.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2403_12820_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_theta(ch):
+    from paper_2403_12820_amd import inputs as I
+    if ch == 32 and os.path.exists(WEIGHTS):
+        th = np.load(WEIGHTS, allow_pickle=False).astype(np.float32)
+        if th.size == I.theta_size(ch):
+            return th, "trained"
+    return I.init_theta(ch, seed=1), "random N(0, 0.02) seed 1"
+
+
+def cpu_baseline(ch, theta, budget_s=10.0):
+    """The FP64 oracle's CNN frame on one 256 x 256 cloth, repeated for about budget_s seconds."""
+    import oracle
+    from paper_2403_12820_amd import inputs as I
+    sc = I.random_scenes([(256, 256)], seed=5)[0]
+    s = sc.state.astype(np.float64)
+    th = theta.astype(np.float64)
+    t0 = time.perf_counter()
+    frames = 0
+    sp, sk = s, s
+    while True:
+        sn, _ = oracle.cnn_forward(256, 256, ch, 1.0, 5e-3, sc.a_ext, sc.pin, th, sp, sk)
+        sp, sk = sk, sn
+        frames += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": frames * 256 * 256 / dt, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d FP64 CNN frames (Ch=%d) of one 256x256 cloth, single thread, %.1f s" % (frames, ch, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--instances", type=int, default=128)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--ch", type=int, default=32)
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (instances would shard "
+              "across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_12820_amd import _lib as L
+    from paper_2403_12820_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mat = I.Material()
+    stride = 10
+    dt_nn = stride * mat.dt
+    sizes = [(args.size, args.size)] * args.instances
+    scenes = I.random_scenes(sizes, seed=5)
+    batch = I.make_batch(scenes)
+    N = batch.total
+    plan = L.Plan.from_batch(batch, dev)
+    theta_np, theta_kind = load_theta(args.ch)
+    theta = torch.tensor(theta_np, device=dev)
+    model = L.make_model(theta, args.ch, L.PECNN_BF16, dt=dt_nn)
+    sim = L.ms_params(mat)
+    s0 = torch.tensor(batch.state, device=dev)
+    a, b, c = s0.clone(), s0.clone(), torch.empty_like(s0)
+    if not args.no_autotune:
+        L.pecnn_autotune(plan, sim, model, a, b, c, reps=5)
+    ms_cfg, cnn_cfg = plan.get_tiles()
+
+    guard = L.Guard()
+    guard.stretch_max, guard.energy_gain_max, guard.check_every, guard.substeps = 1.1, 1.0, args.check_every, stride
+    fb = torch.zeros(batch.n, dtype=torch.int32, device=dev)
+    stats = torch.zeros(4 * batch.n, dtype=torch.float64, device=dev)
+    ws = plan.workspace(L.WS_ROLLOUT)
+
+    # ---- timed region: K network frames of the batch
+    a.copy_(s0)
+    b.copy_(s0)
+    L.pecnn_rollout(plan, model, sim, guard, a, b, args.warmup, fb, stats, ws)
+    torch.cuda.synchronize()
+    a.copy_(s0)
+    b.copy_(s0)
+    fb.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.pecnn_rollout(plan, model, sim, guard, a, b, args.steps, fb, stats, ws)
+    torch.cuda.synchronize()
+    t_roll = time.perf_counter() - t0
+    fell = int((fb != 0).sum().item())
+
+    # ---- the FP32 mass-spring step on the same batch, beside it (stride steps per frame)
+    ms_ws = plan.workspace(L.WS_MS_STEP)
+    x, y = s0.clone(), torch.empty_like(s0)
+    L.cloth_ms_step(plan, sim, x, y, 10, ws=ms_ws)
+    torch.cuda.synchronize()
+    n_ms = args.steps * stride
+    t0 = time.perf_counter()
+    L.cloth_ms_step(plan, sim, x, y, n_ms, ws=ms_ws)
+    torch.cuda.synchronize()
+    t_ms = time.perf_counter() - t0
+
+    # ---- position RMS of the network rollout against the FP32 simulator, FP64 reduction
+    red = torch.zeros(4 * batch.n, dtype=torch.float64, device=dev)
+    L.cloth_reduce_fp64(plan, sim, b, y, red)
+    torch.cuda.synchronize()
+    r = red.cpu().numpy().reshape(-1, 4)
+    width = (batch.W - 1) * batch.h
+    rms = np.sqrt(r[:, 0] / (batch.H * batch.W)) / width
+
+    # ---- dominant kernel alone, HIP events on the launch stream
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    bufs = [s0.clone(), s0.clone(), torch.empty_like(s0)]
+    for i in range(3):
+        L.pecnn_forward(plan, model, bufs[i % 3], bufs[(i + 1) % 3], bufs[(i + 2) % 3], stream=st)
+    e0.record(st)
+    for i in range(args.kernel_reps):
+        L.pecnn_forward(plan, model, bufs[i % 3], bufs[(i + 1) % 3], bufs[(i + 2) % 3], stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_kernel = e0.elapsed_time(e1) / 1e3 / args.kernel_reps
+    ms_e0, ms_e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms_e0.record(st)
+    for i in range(args.kernel_reps):
+        L.cloth_ms_step(plan, sim, x if i % 2 == 0 else y, y if i % 2 == 0 else x, 1, stream=st)
+    ms_e1.record(st)
+    torch.cuda.synchronize()
+    t_ms_kernel = ms_e0.elapsed_time(ms_e1) / 1e3 / args.kernel_reps
+    alg_bytes = CNN_BYTES_PER_NODE * N
+    achieved = alg_bytes / t_kernel / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("source_hash") == kernel_source_hash() and tr.get("nodes") == N:
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    value = N * args.steps / t_roll
+    ms_rate = N * n_ms / t_ms
+    out = {
+        "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_roll / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {
+            "workload": "bf16 CNN rollout (Ch=%d) of %d cloths of %dx%d, guard + FP64 reductions every %d frames"
+                        % (args.ch, args.instances, args.size, args.size, args.check_every),
+            "instances": args.instances, "grid": [args.size, args.size], "nodes": N, "channels": args.ch,
+            "weights": theta_kind, "tiles": {"ms_cfg": ms_cfg, "cnn_cfg": cnn_cfg},
+            "frame_dt": dt_nn, "sim_dt": mat.dt, "stride": stride,
+            "sim_equivalent_node_steps_per_s": value * stride,
+            "ms_fp32_node_steps_per_s": ms_rate,
+            "cnn_vs_ms_raw": value / ms_rate,
+            "cnn_vs_ms_sim_equivalent": value * stride / ms_rate,
+            "rms_vs_fp32_ms_width_mean": float(rms.mean()), "rms_vs_fp32_ms_width_max": float(rms.max()),
+            "fallback_instances": fell,
+            "ms_kernel_gbs": MS_BYTES_PER_NODE * N / t_ms_kernel / 1e9,
+            "cnn_kernel_ms": t_kernel * 1e3, "ms_kernel_ms": t_ms_kernel * 1e3,
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "cnn_fwd_kernel<32,bf16>", "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.ch, theta_np, args.cpu_seconds)
+    plan.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

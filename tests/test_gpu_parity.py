@@ -185,11 +185,15 @@ def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch):
     e_exact = rel_inf(dv, dv_exact)
     e_emu = rel_inf(dv, dv_emu)
     assert e_exact <= 1e-2, e_exact
-    # same operand rounding: only FP32 accumulation order and rare bf16 rounding flips of
-    # intermediate features differ; the typical node agrees to FP32 accumulation accuracy
-    assert e_emu <= 2e-3, e_emu
-    med = np.median(np.abs(dv - dv_emu)) / np.abs(dv_emu).max()
-    assert med <= 1e-5, med
+    # Same operand rounding as the emulated oracle: the FP32 (GPU) and FP64 (oracle) accumulations
+    # differ by ~1e-7 relative, which is enough to send an intermediate feature to the other bf16
+    # neighbour now and then. Such a flip moves one head term by at most one bf16 ulp (2^-8 of the
+    # feature), so no node may differ by more than 2^-8 of the output scale; and the typical node,
+    # with no flip, agrees to FP32 accumulation accuracy.
+    assert e_emu <= 2.0 ** -8, e_emu
+    per_node = np.abs(dv - dv_emu).max(axis=0) / np.abs(dv_emu).max()
+    assert np.median(per_node) <= 1e-5, np.median(per_node)
+    assert np.quantile(per_node, 0.99) <= 2e-4, np.quantile(per_node, 0.99)
 
 
 def test_cnn_tile_configs_bitwise_equal(torch_mod, L):
@@ -333,3 +337,123 @@ def test_gather_windows(torch_mod, L):
         for t in range(4):
             np.testing.assert_array_equal(o[t, :, w * npw:(w + 1) * npw],
                                           traj[fr[w] + t, :, inst[w] * npw:(inst[w] + 1) * npw])
+
+
+# ------------------------------------------------------------------ rollout orchestration
+def _rollout_setup(L, torch, sizes, seed, ch=32, prec=0, scale=5.0, dt=5e-3):
+    batch, s0, s1, th = _cnn_inputs(sizes, seed, ch, scale)
+    plan = L.Plan.from_batch(batch)
+    t = dev_tensor(th)
+    model = L.make_model(t, ch, prec, dt=dt)
+    return batch, plan, model, s0, s1
+
+
+def _forward_loop(L, torch, plan, model, s0, s1, n):
+    bufs = [dev_tensor(s0), dev_tensor(s1), torch.zeros(6, s0.shape[1], device="cuda")]
+    for _ in range(n):
+        L.pecnn_forward(plan, model, bufs[0], bufs[1], bufs[2])
+        bufs = [bufs[1], bufs[2], bufs[0]]
+    torch.cuda.synchronize()
+    return bufs[0].cpu().numpy(), bufs[1].cpu().numpy()
+
+
+def _guard(L, stretch=10.0, gain=1e9, every=0, sub=10):
+    g = L.Guard()
+    g.stretch_max, g.energy_gain_max, g.check_every, g.substeps = stretch, gain, every, sub
+    return g
+
+
+@pytest.mark.parametrize("n,every", [(7, 0), (10, 3), (4, 10)])
+def test_rollout_equals_forward_loop(torch_mod, L, n, every):
+    torch = torch_mod
+    for prec in (0, 1):
+        batch, plan, model, s0, s1 = _rollout_setup(L, torch, [(40, 70), (16, 16), (3, 9)], 1000, prec=prec)
+        ref_p, ref_c = _forward_loop(L, torch, plan, model, s0, s1, n)
+        a, b = dev_tensor(s0), dev_tensor(s1)
+        fb = torch.zeros(batch.n, dtype=torch.int32, device="cuda")
+        stats = torch.zeros(4 * batch.n, dtype=torch.float64, device="cuda")
+        sim = L.ms_params(MAT)
+        for _ in range(2):  # the second call replays cached graphs
+            a.copy_(dev_tensor(s0))
+            b.copy_(dev_tensor(s1))
+            L.pecnn_rollout(plan, model, sim, _guard(L, every=every), a, b, n, fb, stats)
+            torch.cuda.synchronize()
+            assert np.array_equal(a.cpu().numpy(), ref_p) and np.array_equal(b.cpu().numpy(), ref_c)
+        assert np.all(fb.cpu().numpy() == 0)
+        st = stats.cpu().numpy().reshape(-1, 4)
+        assert np.all(st[:, 3] == -1)
+
+
+def test_rollout_forced_fallback_matches_mass_spring(torch_mod, L):
+    """stretch bound below 1: every instance trips at the first check (after 'every' frames) and
+    continues with 'sub' mass-spring steps per frame, bit-for-bit equal to a plain run."""
+    torch = torch_mod
+    n, every, sub = 7, 3, 4
+    batch, plan, model, s0, s1 = _rollout_setup(L, torch, [(24, 40), (9, 9)], 1100)
+    sim = L.ms_params(MAT)
+    a, b = dev_tensor(s0), dev_tensor(s1)
+    fb = torch.zeros(batch.n, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(4 * batch.n, dtype=torch.float64, device="cuda")
+    L.pecnn_rollout(plan, model, sim, _guard(L, stretch=0.5, every=every, sub=sub), a, b, n, fb, stats)
+    torch.cuda.synchronize()
+    assert np.all(fb.cpu().numpy() == 1)
+    st = stats.cpu().numpy().reshape(-1, 4)
+    assert np.all(st[:, 3] == every)
+    # reference: 'every' network frames, then (n - every) * sub mass-spring steps
+    rp, rc = _forward_loop(L, torch, plan, model, s0, s1, every)
+    cur = dev_tensor(rc)
+    prev = None
+    for _ in range(n - every):
+        nxt = torch.zeros_like(cur)
+        L.cloth_ms_step(plan, sim, cur, nxt, sub)
+        prev, cur = cur, nxt
+    torch.cuda.synchronize()
+    assert np.array_equal(b.cpu().numpy(), cur.cpu().numpy())
+    assert np.array_equal(a.cpu().numpy(), prev.cpu().numpy())
+
+
+def test_rollout_preset_fallback_instance(torch_mod, L):
+    """A caller-preset flag sends that instance to the mass-spring step from the first frame while
+    the others keep the network."""
+    torch = torch_mod
+    n, sub = 5, 3
+    batch, plan, model, s0, s1 = _rollout_setup(L, torch, [(20, 20), (12, 30)], 1200)
+    sim = L.ms_params(MAT)
+    a, b = dev_tensor(s0), dev_tensor(s1)
+    fb = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    L.pecnn_rollout(plan, model, sim, _guard(L, every=0, sub=sub), a, b, n, fb, None)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    rp, rc = _forward_loop(L, torch, plan, model, s0, s1, n)
+    s0i = batch.instance(0)
+    assert np.array_equal(got[:, s0i], rc[:, s0i])
+    ref1 = oracle.batch_ms_step(batch, s1, MAT, n * sub)
+    s1i = batch.instance(1)
+    assert np.abs(got[:3, s1i] - ref1[:3, s1i]).max() <= 1e-5 * 29 * batch.h[1]
+
+
+def test_autotune_picks_a_config(torch_mod, L):
+    torch = torch_mod
+    batch, plan, model, s0, s1 = _rollout_setup(L, torch, [(128, 128), (64, 64)], 1300, prec=1)
+    a, b, c = dev_tensor(s0), dev_tensor(s1), torch.zeros(6, batch.total, device="cuda")
+    ms, cn = L.pecnn_autotune(plan, L.ms_params(MAT), model, a, b, c, reps=3)
+    assert all(t > 0 for t in ms) and all(t > 0 for t in cn)
+    m_cfg, c_cfg = plan.get_tiles()
+    assert ms[m_cfg] == min(ms) and cn[c_cfg] == min(cn)
+
+
+def test_invalid_arguments_return_errors(torch_mod, L):
+    torch = torch_mod
+    batch, plan, model, s0, s1 = _rollout_setup(L, torch, [(8, 8)], 1400)
+    a = dev_tensor(s0)
+    with pytest.raises(L.PecnnError):
+        L.pecnn_forward(plan, model, a, a, a)  # output overlaps input
+    bad = L.make_model(model._theta_ref, 24, 0)
+    with pytest.raises(L.PecnnError):
+        L.pecnn_forward(plan, bad, a, dev_tensor(s1), torch.zeros_like(a))
+    p = L.ms_params(MAT, dt=-1.0)
+    with pytest.raises(L.PecnnError):
+        L.cloth_ms_step(plan, p, a, torch.zeros_like(a))
+    with pytest.raises(L.PecnnError):
+        L.cloth_ms_step(plan, L.ms_params(MAT), a, torch.zeros_like(a), 3, ws=torch.zeros(8, dtype=torch.uint8,
+                                                                                             device="cuda"))
