@@ -48,7 +48,8 @@ typedef enum {
 typedef struct {
   int32_t n;              /* number of instances, 1 .. 65536 */
   const int32_t* H;       /* rows per instance, >= 1 */
-  const int32_t* W;       /* columns per instance, >= 1; H*W >= 2 and H*W < 2^24 */
+  const int32_t* W;       /* columns per instance, >= 1; H*W >= 2 and H*W < 2^24; total nodes
+                             N_total < 2^32 / 24 (a state stays below 4 GiB) */
   const float* h;         /* rest spacing of the grid (m), > 0: rest lengths h, sqrt(2)h, 2h */
   const float* mass;      /* node mass (kg), > 0 (section 3.1: mass points) */
   const float* a_ext;     /* constant external acceleration per instance (wind), [n][3] */
@@ -69,7 +70,7 @@ int pecnn_plan_destroy(pecnn_plan* plan);
 int64_t pecnn_plan_nodes(const pecnn_plan* plan);   /* N_total, or -1 for a null plan */
 
 /* Tile configurations chosen for the mass-spring step and the CNN cell (see pecnn_autotune).
-   ms_cfg in [0, 5), cnn_cfg in [0, 3); -1 keeps the current choice. */
+   ms_cfg in [0, 5), cnn_cfg in [0, 4); -1 keeps the current choice. */
 int pecnn_plan_set_tiles(pecnn_plan* plan, int32_t ms_cfg, int32_t cnn_cfg);
 int pecnn_plan_get_tiles(const pecnn_plan* plan, int32_t* ms_cfg, int32_t* cnn_cfg);
 
@@ -212,7 +213,7 @@ int pecnn_workspace_bytes(const pecnn_plan* plan, const pecnn_model* model, int3
    (synchronous: runs 'reps' timed launches of each on 'stream' using the given buffers, which
    are overwritten) and store the fastest in the plan. s_a, s_b, s_c: device [6][N_total]
    scratch states (contents preserved are not guaranteed). ms_ms/cnn_ms (host, nullable, length
-   5 and 3) receive the mean milliseconds per launch of each configuration. */
+   5 and 4) receive the mean milliseconds per launch of each configuration. */
 int pecnn_autotune(pecnn_plan* plan, const cloth_ms_params* p, const pecnn_model* model,
                    float* s_a, float* s_b, float* s_c, int32_t reps, float* ms_ms, float* cnn_ms,
                    void* stream);

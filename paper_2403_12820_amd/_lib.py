@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libpecnn.so")
 
 PECNN_FP32, PECNN_BF16 = 0, 1
 WS_MS_STEP, WS_BACKWARD, WS_ROLLOUT, WS_REDUCE = 0, 1, 2, 3
-N_MS_CFG, N_CNN_CFG = 5, 3
+N_MS_CFG, N_CNN_CFG = 5, 4
 
 
 class PecnnError(RuntimeError):

@@ -14,7 +14,9 @@ LIB = os.path.join(OUT_DIR, "libpecnn.so")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-    "-Wno-unknown-pragmas",
+    "-Wno-unknown-pragmas", "-ffp-contract=off",
+    # keep MFMA results in VGPRs (no accumulator-register copies before VALU use)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     # packed FP32 VALU forms are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

@@ -235,7 +235,7 @@ static int check_desc(const pecnn_batch_desc* d) {
     }
     tot += hw;
   }
-  if (tot >= ((int64_t)1 << 31) / 6) { set_error("batch too large (%lld nodes)", (long long)tot); return PECNN_E_SHAPE; }
+  if (tot >= ((int64_t)1 << 32) / 24) { set_error("batch too large (%lld nodes)", (long long)tot); return PECNN_E_SHAPE; }
   return PECNN_OK;
 }
 

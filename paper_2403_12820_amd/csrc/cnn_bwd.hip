@@ -96,8 +96,8 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
       F[(L.ud + t) * N] = ud;
 #pragma unroll
       for (int r = 0; r < CH; ++r) {
-        phi[r] += th[r * 54 + t] * uk;
-        xi[r] += th[r * 54 + t] * ud;
+        phi[r] = __builtin_fmaf(th[r * 54 + t], uk, phi[r]);
+        xi[r] = __builtin_fmaf(th[r * 54 + t], ud, xi[r]);
       }
     }
   }
@@ -112,8 +112,8 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
     const float pc = my[c];
 #pragma unroll
     for (int r = 0; r < CH; ++r) {
-      a[r] += th[oA + r * CH + c] * pc;
-      bb[r] += th[oB + r * CH + c] * pc;
+      a[r] = __builtin_fmaf(th[oA + r * CH + c], pc, a[r]);
+      bb[r] = __builtin_fmaf(th[oB + r * CH + c], pc, bb[r]);
     }
   }
   // adjoint of eq. (5)
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
   for (int r = 0; r < CH; ++r) {
     const float gar = my[r], gbr = my[CH + r];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) phi[c] += th[oA + r * CH + c] * gar + th[oB + r * CH + c] * gbr;
+    for (int c = 0; c < CH; ++c) phi[c] = __builtin_fmaf(th[oB + r * CH + c], gbr, __builtin_fmaf(th[oA + r * CH + c], gar, phi[c]));
   }
 #pragma unroll
   for (int c = 0; c < CH; ++c) F[(L.gphi + c) * N] = phi[c];
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
     float gk = 0.f, gd = 0.f;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      gk += th[c * 54 + t] * phi[c];
-      gd += th[c * 54 + t] * xi[c];
+      gk = __builtin_fmaf(th[c * 54 + t], phi[c], gk);
+      gd = __builtin_fmaf(th[c * 54 + t], xi[c], gd);
     }
     F[(L.gus + t) * N] = gk + gd;
     F[(L.gud + t) * N] = gd;
@@ -306,10 +306,10 @@ __global__ __launch_bounds__(256) void bwd_wgrad_kernel(
       if (y1[k] < 0) {
         for (int n = 0; n < SUB; ++n) s += lds[x1[k] * SUB + n];
       } else if (x2[k] < 0) {
-        for (int n = 0; n < SUB; ++n) s += lds[x1[k] * SUB + n] * lds[y1[k] * SUB + n];
+        for (int n = 0; n < SUB; ++n) s = __builtin_fmaf(lds[x1[k] * SUB + n], lds[y1[k] * SUB + n], s);
       } else {
         for (int n = 0; n < SUB; ++n)
-          s += lds[x1[k] * SUB + n] * lds[y1[k] * SUB + n] + lds[x2[k] * SUB + n] * lds[y2[k] * SUB + n];
+          s = __builtin_fmaf(lds[x2[k] * SUB + n], lds[y2[k] * SUB + n], __builtin_fmaf(lds[x1[k] * SUB + n], lds[y1[k] * SUB + n], s));
       }
       acc[k] = s;
     }

@@ -26,8 +26,8 @@ constexpr int kNumMsCfg = 5;
 constexpr MsCfg kMsCfg[kNumMsCfg] = {{32, 8, 1}, {64, 4, 1}, {16, 16, 1}, {32, 16, 2}, {64, 8, 2}};
 // CNN cell: TX x TY nodes per workgroup of 4 waves; TX is a multiple of 16 (one MFMA column block).
 struct CnnCfg { int tx, ty; };
-constexpr int kNumCnnCfg = 3;
-constexpr CnnCfg kCnnCfg[kNumCnnCfg] = {{64, 4}, {32, 8}, {16, 16}};
+constexpr int kNumCnnCfg = 4;
+constexpr CnnCfg kCnnCfg[kNumCnnCfg] = {{64, 4}, {32, 8}, {16, 16}, {64, 8}};
 // Node-parallel kernels (reductions, backward): flat chunks of kChunk nodes per instance.
 constexpr int kChunk = 256;
 constexpr int kNumCfg = kNumMsCfg + kNumCnnCfg + 1;
@@ -68,6 +68,18 @@ __device__ __forceinline__ void xcd_tile_range(int n_tiles, int& first, int& str
   first = base + slot;
   stride = wg_here;
   count = (first < end) ? (end - first + stride - 1) / stride : 0;
+}
+
+// Global accesses through a 32-bit byte offset from a base pointer, which lets the compiler use the
+// scalar-base + vector-offset addressing mode (batches are validated to stay below 4 GiB per
+// state: 24 N_total < 2^32).
+template <typename T>
+__device__ __forceinline__ T gld(const T* __restrict__ base, unsigned idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(float));
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* __restrict__ base, unsigned idx, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(float)) = v;
 }
 
 struct MsParamsDev {

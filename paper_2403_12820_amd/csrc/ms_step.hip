@@ -1,10 +1,11 @@
 // Mass-spring cloth step (section 3.1, eqs. 1, 2, 4, 5) on gfx950.
 //
 // One workgroup owns a TX x TY tile of one instance; the six state planes of the tile plus a
-// two-node halo (the stencil radius of the bending springs) are staged in LDS with coalesced
-// row loads, then each thread integrates RY nodes. Workgroups are persistent over the batch's
-// tile list, with a contiguous tile range per XCD so that halo rows shared by neighbouring
-// tiles are served by one L2.
+// two-node halo (the stencil radius of the bending springs) are staged in LDS, then each thread
+// integrates RY nodes. Workgroups are persistent over the batch's tile list: the next tile's
+// loads (16-byte where the rows allow it, plus its pin flags) are issued into registers before
+// the current tile is computed, so HBM latency hides behind the spring arithmetic. Each XCD
+// walks a contiguous tile range, so halo rows shared by neighbouring tiles meet in one L2.
 #include "common.hpp"
 
 namespace pecnn {
@@ -22,89 +23,173 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_in, float* __restrict__ s_out,
     int64_t N, MsParamsDev P, const uint8_t* __restrict__ active) {
-  constexpr int HX = TX + 4, HY = TY + 4;
   constexpr int NT = TX * (TY / RY);
-  __shared__ float lds[6][HY][HX];
+  constexpr int RS = TX + 8;  // LDS row stride: tile column j at 4 + j, halo columns 2, 3 and 4+TX, 5+TX
+  constexpr int HY = TY + 4;
+  constexpr int PLN = HY * RS;
+  constexpr int QV = TX / 4;
+  constexpr int NROW = 6 * HY;
+  constexpr int NV = NROW * QV, NVT = (NV + NT - 1) / NT;
+  constexpr int NH = NROW * 4, NHT = (NH + NT - 1) / NT;
+  constexpr int NP = TX * TY, NPT = (NP + NT - 1) / NT;
+  __shared__ __align__(16) float lds[6 * PLN];
+  __shared__ uint8_t tP[NP];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % TX;
+  const int ty0 = (tid / TX) * RY;
+  float4 pv[NVT];
+  float ph[NHT];
+  uint8_t pp[NPT];
 
   int first, stride, count;
   xcd_tile_range(n_tiles, first, stride, count);
-  const int tx = threadIdx.x % TX;
-  const int ty0 = (threadIdx.x / TX) * RY;
 
-  for (int it = 0; it < count; ++it) {
+  auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
     const int t = first + it * stride;
     const int b = find_instance(prefix, n_inst, t);
-    if (active != nullptr && active[b] == 0) continue;  // uniform over the workgroup
-    const InstDev I = inst[b];
+    if (active != nullptr && active[b] == 0) return false;
+    I = inst[b];
     const int lt = t - prefix[b];
     const int tiles_x = (I.W + TX - 1) / TX;
-    const int r0 = (lt / tiles_x) * TY;
-    const int c0 = (lt % tiles_x) * TX;
-    const float* __restrict__ src = s_in + I.off;
-
-    for (int e = threadIdx.x; e < 6 * HY * HX; e += NT) {
-      const int c = e / (HY * HX);
-      const int rem = e - c * (HY * HX);
-      const int rr = rem / HX;
-      const int cc = rem - rr * HX;
-      const int gi = r0 + rr - 2, gj = c0 + cc - 2;
-      float v = 0.f;
-      if (gi >= 0 && gi < I.H && gj >= 0 && gj < I.W) v = src[c * N + (int64_t)gi * I.W + gj];
-      lds[c][rr][cc] = v;
-    }
-    __syncthreads();
-
-    const float L[3] = {I.h, I.h * 1.41421356237309515f, 2.f * I.h};
-    const float tiny = 1e-24f * I.h * I.h;
-    const float inv_m = 1.f / I.mass;
+    r0 = (lt / tiles_x) * TY;
+    c0 = (lt % tiles_x) * TX;
+    return true;
+  };
+  // Issue the loads of a tile and its two-node halo (rows and columns clamped to the grid; the
+  // clamped copies are never used as springs, whose ends are checked against the grid).
+  auto issue = [&](const InstDev& I, int r0, int c0) {
+    const bool vec = ((I.W & 3) == 0) && ((I.off & 3) == 0) && ((N & 3) == 0);
 #pragma unroll
-    for (int ry = 0; ry < RY; ++ry) {
-      const int ly = ty0 + ry;
-      const int i = r0 + ly, j = c0 + tx;
-      if (i < I.H && j < I.W) {
-        const int64_t p = I.off + (int64_t)i * I.W + j;
-        const int hy = ly + 2, hx = tx + 2;
-        const float x0 = lds[0][hy][hx], x1 = lds[1][hy][hx], x2 = lds[2][hy][hx];
-        const float v0 = lds[3][hy][hx], v1 = lds[4][hy][hx], v2 = lds[5][hy][hx];
-        float n0, n1, n2;
-        if (pin[p]) {
-          n0 = n1 = n2 = 0.f;
+    for (int i = 0; i < NVT; ++i) {
+      const int j = tid + NT * i;
+      if (NV % NT == 0 || j < NV) {
+        const int row = j / QV, q = j - (j / QV) * QV;
+        const int c = row / HY, rr = row - (row / HY) * HY;
+        const int gi = min(max(r0 + rr - 2, 0), I.H - 1);
+        const int col = c0 + 4 * q;
+        const unsigned rb = (unsigned)(c * (int)N + (int)I.off + gi * I.W);
+        if (vec && col + 3 < I.W) {
+          pv[i] = gld(reinterpret_cast<const float4*>(s_in), rb + col);
         } else {
-          // eq. (4) plus the wind: m (g + a_ext) - d v
-          float f0 = I.mass * (P.g[0] + I.ax) - P.drag * v0;
-          float f1 = I.mass * (P.g[1] + I.ay) - P.drag * v1;
-          float f2 = I.mass * (P.g[2] + I.az) - P.drag * v2;
-#pragma unroll
-          for (int q = 0; q < 12; ++q) {
-            const Spring S = kSprings[q];
-            const int ii = i + S.dy, jj = j + S.dx;
-            if (ii < 0 || ii >= I.H || jj < 0 || jj >= I.W) continue;
-            const int ny = hy + S.dy, nx = hx + S.dx;
-            const float d0 = x0 - lds[0][ny][nx], d1 = x1 - lds[1][ny][nx], d2 = x2 - lds[2][ny][nx];
-            const float w0 = v0 - lds[3][ny][nx], w1 = v1 - lds[4][ny][nx], w2 = v2 - lds[5][ny][nx];
-            const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            if (!(r2 > tiny)) continue;
-            const float ir = __builtin_amdgcn_rsqf(r2);
-            const float r = r2 * ir;
-            const float ce = -P.k[S.fam] * (r - L[S.fam]) * ir;            // eq. (1)
-            const float cd = -P.mu * (w0 * d0 + w1 * d1 + w2 * d2) * ir * ir;  // eq. (2)
-            const float cf = ce + cd;
-            f0 += cf * d0;
-            f1 += cf * d1;
-            f2 += cf * d2;
-          }
-          // eq. (5): semi-implicit Euler
-          const float s = P.dt * inv_m;
-          n0 = v0 + s * f0;
-          n1 = v1 + s * f1;
-          n2 = v2 + s * f2;
+          pv[i] = make_float4(gld(s_in, rb + min(col, I.W - 1)), gld(s_in, rb + min(col + 1, I.W - 1)),
+                              gld(s_in, rb + min(col + 2, I.W - 1)), gld(s_in, rb + min(col + 3, I.W - 1)));
         }
-        s_out[3 * N + p] = n0;
-        s_out[4 * N + p] = n1;
-        s_out[5 * N + p] = n2;
-        s_out[0 * N + p] = x0 + P.dt * n0;
-        s_out[1 * N + p] = x1 + P.dt * n1;
-        s_out[2 * N + p] = x2 + P.dt * n2;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NHT; ++i) {
+      const int j = tid + NT * i;
+      if (NH % NT == 0 || j < NH) {
+        const int row = j >> 2, side = j & 3;  // columns c0-2, c0-1, c0+TX, c0+TX+1
+        const int c = row / HY, rr = row - (row / HY) * HY;
+        const int gi = min(max(r0 + rr - 2, 0), I.H - 1);
+        const int gj = min(max(side < 2 ? c0 - 2 + side : c0 + TX + side - 2, 0), I.W - 1);
+        ph[i] = gld(s_in, (unsigned)(c * (int)N + (int)I.off + gi * I.W + gj));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int j = tid + NT * i;
+      if (NP % NT == 0 || j < NP) {
+        const int ly = j / TX, lx = j - (j / TX) * TX;
+        const int gi = r0 + ly, gj = c0 + lx;
+        pp[i] = (gi < I.H && gj < I.W) ? pin[(unsigned)((int)I.off + gi * I.W + gj)] : (uint8_t)0;
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < NVT; ++i) {
+      const int j = tid + NT * i;
+      if (NV % NT == 0 || j < NV) {
+        const int row = j / QV, q = j - (j / QV) * QV;
+        const int c = row / HY, rr = row - (row / HY) * HY;
+        *reinterpret_cast<float4*>(&lds[c * PLN + rr * RS + 4 + 4 * q]) = pv[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NHT; ++i) {
+      const int j = tid + NT * i;
+      if (NH % NT == 0 || j < NH) {
+        const int row = j >> 2, side = j & 3;
+        const int c = row / HY, rr = row - (row / HY) * HY;
+        lds[c * PLN + rr * RS + (side < 2 ? 2 + side : 2 + TX + side)] = ph[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int j = tid + NT * i;
+      if (NP % NT == 0 || j < NP) tP[j] = pp[i];
+    }
+  };
+
+  InstDev I;
+  int r0 = 0, c0 = 0;
+  bool have = count > 0 && decode(0, I, r0, c0);
+  if (have) issue(I, r0, c0);
+  for (int it = 0; it < count; ++it) {
+    const bool cur = have;
+    const InstDev Ic = I;
+    const int rc0 = r0, cc0 = c0;
+    if (cur) stage();
+    __syncthreads();
+    have = (it + 1 < count) && decode(it + 1, I, r0, c0);
+    if (have) issue(I, r0, c0);
+
+    if (cur) {
+      const float L[3] = {Ic.h, Ic.h * 1.41421356237309515f, 2.f * Ic.h};
+      const float tiny = 1e-24f * Ic.h * Ic.h;
+      const float sc = P.dt / Ic.mass;
+      const float nmu = -P.mu;
+      // eq. (4) plus the wind, constant part: m (g + a_ext)
+      const float g0 = Ic.mass * (P.g[0] + Ic.ax), g1 = Ic.mass * (P.g[1] + Ic.ay), g2 = Ic.mass * (P.g[2] + Ic.az);
+#pragma unroll
+      for (int ry = 0; ry < RY; ++ry) {
+        const int ly = ty0 + ry;
+        const int i = rc0 + ly, j = cc0 + tx;
+        if (i < Ic.H && j < Ic.W) {
+          const unsigned p = (unsigned)((int)Ic.off + i * Ic.W + j);
+          const int e = (ly + 2) * RS + 4 + tx;
+          const float x0 = lds[e], x1 = lds[PLN + e], x2 = lds[2 * PLN + e];
+          const float v0 = lds[3 * PLN + e], v1 = lds[4 * PLN + e], v2 = lds[5 * PLN + e];
+          float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+          if (!tP[ly * TX + tx]) {
+            float f0 = __builtin_fmaf(-P.drag, v0, g0);
+            float f1 = __builtin_fmaf(-P.drag, v1, g1);
+            float f2 = __builtin_fmaf(-P.drag, v2, g2);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+              const Spring S = kSprings[q];
+              const int ii = i + S.dy, jj = j + S.dx;
+              if (ii < 0 || ii >= Ic.H || jj < 0 || jj >= Ic.W) continue;  // spring needs both ends
+              const int en = e + S.dy * RS + S.dx;
+              const float d0 = x0 - lds[en], d1 = x1 - lds[PLN + en], d2 = x2 - lds[2 * PLN + en];
+              const float w0 = v0 - lds[3 * PLN + en], w1 = v1 - lds[4 * PLN + en], w2 = v2 - lds[5 * PLN + en];
+              const float r2 = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
+              if (!(r2 > tiny)) continue;  // a degenerate spring (r ~ 0) contributes nothing
+              const float ir = __builtin_amdgcn_rsqf(r2);
+              const float r = r2 * ir;
+              const float ce = (P.k[S.fam] * (L[S.fam] - r)) * ir;       // eq. (1): -k (r - L) / r
+              const float vx = __builtin_fmaf(w2, d2, __builtin_fmaf(w1, d1, w0 * d0));
+              const float cf = __builtin_fmaf((nmu * ir) * ir, vx, ce);  // eq. (2): -mu (v.x) / r^2
+              f0 = __builtin_fmaf(cf, d0, f0);
+              f1 = __builtin_fmaf(cf, d1, f1);
+              f2 = __builtin_fmaf(cf, d2, f2);
+            }
+            // eq. (5): semi-implicit Euler
+            n0 = __builtin_fmaf(sc, f0, v0);
+            n1 = __builtin_fmaf(sc, f1, v1);
+            n2 = __builtin_fmaf(sc, f2, v2);
+          }
+          const int N32 = (int)N;
+          gst(s_out, 3 * N32 + p, n0);
+          gst(s_out, 4 * N32 + p, n1);
+          gst(s_out, 5 * N32 + p, n2);
+          gst(s_out, p, __builtin_fmaf(P.dt, n0, x0));
+          gst(s_out, N32 + p, __builtin_fmaf(P.dt, n1, x1));
+          gst(s_out, 2 * N32 + p, __builtin_fmaf(P.dt, n2, x2));
+        }
       }
     }
     __syncthreads();

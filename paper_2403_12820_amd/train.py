@@ -1,0 +1,287 @@
+"""Training driver of the physics-embedded CNN (section 3.2.1) over the pecnn C ABI.
+
+Python only sequences calls; every step runs in the HIP library:
+  * trajectories: batched mass-spring steps (cloth_ms_step), frames saved every `stride` steps;
+  * normalisation: RMS one-frame increments of x and v from the loss kernel;
+  * minibatches: random (scene, frame) windows gathered on the device (pecnn_gather_windows);
+  * loss: data term of eq. (8) on the one-step prediction and on an 8-step unrolled prediction
+    (pecnn_loss_mse), alpha = 0;
+  * gradients: back-propagation through the unrolled frames (pecnn_backward, BPTT);
+  * update: Adam (pecnn_adam_step), lr 1e-3.
+
+    python -m paper_2403_12820_amd.train --scenes 64 --size 64 --iters 20000 --out weights/pecnn_ch32.npy
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+class Trajectories:
+    """Mass-spring trajectories of a batch of scenes, saved every `stride` simulator steps."""
+
+    def __init__(self, scenes, mat, n_frames, stride, device="cuda"):
+        import torch
+        from . import _lib as L
+        self.batch = I.make_batch(scenes)
+        self.scenes = scenes
+        self.plan = L.Plan.from_batch(self.batch, device)
+        self.sim = L.ms_params(mat)
+        self.n_frames, self.stride = n_frames, stride
+        N = self.batch.total
+        self.frames = torch.empty(n_frames, 6, N, device=device)
+        self.frames[0].copy_(torch.from_numpy(self.batch.state))
+        ws = self.plan.workspace(L.WS_MS_STEP)
+        for f in range(1, n_frames):
+            L.cloth_ms_step(self.plan, self.sim, self.frames[f - 1], self.frames[f], stride, ws=ws)
+        torch.cuda.synchronize()
+        self.off = torch.tensor(self.batch.node_off, dtype=torch.int64, device=device)
+
+    def increment_scales(self):
+        """RMS over free nodes and frames of the one-frame increments of x and of v (loss kernel)."""
+        import torch
+        from . import _lib as L
+        n_free = int((self.batch.pin == 0).sum())
+        acc = torch.zeros(2, dtype=torch.float64, device=self.frames.device)
+        big = 1e30
+        for f in range(self.n_frames - 1):
+            # with the other scale huge, the loss value is the mean squared increment of one field
+            L.pecnn_loss_mse(self.plan, self.frames[f + 1], self.frames[f], 1.0, big, 1.0, n_free, acc[0:1], None)
+            L.pecnn_loss_mse(self.plan, self.frames[f + 1], self.frames[f], big, 1.0, 1.0, n_free, acc[1:2], None)
+        torch.cuda.synchronize()
+        m = acc.cpu().numpy() / (self.n_frames - 1)
+        return float(math.sqrt(m[0])), float(math.sqrt(m[1]))
+
+
+class WindowBatch:
+    """A minibatch of training windows: n_win cloths of one grid size, each a random
+    (scene, frame) window of n_unroll + 2 frames (S^{k-1}, S^k, S^{k+1..k+n_unroll})."""
+
+    def __init__(self, traj: Trajectories, scene_ids, n_win, n_unroll, device="cuda"):
+        import torch
+        self.traj, self.n_win, self.n_unroll = traj, n_win, n_unroll
+        self.scene_ids = np.asarray(scene_ids, np.int32)
+        sc0 = traj.scenes[int(self.scene_ids[0])]
+        self.H, self.W = sc0.H, sc0.W
+        self.npw = self.H * self.W
+        for b in self.scene_ids:
+            assert traj.scenes[int(b)].H == self.H and traj.scenes[int(b)].W == self.W
+        self.buf = torch.empty(n_unroll + 2, 6, n_win * self.npw, device=device)
+        self.inst = torch.empty(n_win, dtype=torch.int32, device=device)
+        self.frame = torch.empty(n_win, dtype=torch.int32, device=device)
+        self.device = device
+
+    def sample(self, rng: np.random.Generator):
+        """Draw windows uniformly over (scene, start frame); returns a plan for the minibatch."""
+        import torch
+        from . import _lib as L
+        T = self.traj
+        scenes = self.scene_ids[rng.integers(0, len(self.scene_ids), self.n_win)]
+        k0 = rng.integers(0, T.n_frames - (self.n_unroll + 1), self.n_win).astype(np.int32)
+        self.inst.copy_(torch.from_numpy(scenes.astype(np.int32)))
+        self.frame.copy_(torch.from_numpy(k0))
+        L.pecnn_gather_windows(T.frames, T.batch.total, T.n_frames, T.off, T.batch.n, self.inst, self.frame,
+                               self.n_win, self.npw, self.n_unroll + 2, self.buf)
+        sc = [T.scenes[int(b)] for b in scenes]
+        pins = np.concatenate([s.pin for s in sc])
+        plan = L.Plan([s.H for s in sc], [s.W for s in sc], [s.h for s in sc], [s.mass for s in sc],
+                      np.array([s.a_ext for s in sc], np.float32), pins, self.device)
+        return plan, int((pins == 0).sum())
+
+
+class Trainer:
+    def __init__(self, ch=32, dt_nn=5e-3, lr=1e-3, theta=None, seed=1, device="cuda"):
+        import torch
+        from . import _lib as L
+        self.ch, self.dt_nn, self.lr = ch, dt_nn, lr
+        th = I.init_theta(ch, seed=seed) if theta is None else np.asarray(theta, np.float32)
+        self.theta = torch.tensor(th, device=device)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.g = torch.zeros_like(self.theta)
+        self.t = 0
+        self.model = L.make_model(self.theta, ch, L.PECNN_FP32, dt=dt_nn)
+        self.device = device
+
+    def _buffers(self, plan, U, N):
+        import torch
+        from . import _lib as L
+        if getattr(self, "_N", None) != (U, N):
+            self._N = (U, N)
+            self.pred = torch.empty(U, 6, N, device=self.device)
+            self.grads = torch.empty(U, 6, N, device=self.device)
+            self.loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+            self.ws_r = plan.workspace(L.WS_REDUCE)
+            self.ws_b = plan.workspace(L.WS_BACKWARD, self.model)
+
+    def step(self, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0, lr=None):
+        """One iteration: unrolled forward, loss, BPTT, Adam. Returns the loss (device scalar)."""
+        from . import _lib as L
+        U = wb.n_unroll
+        N = wb.n_win * wb.npw
+        self._buffers(plan, U, N)
+        pred, grads = self.pred, self.grads
+        S = [wb.buf[0], wb.buf[1]]  # S^{k-1}, S^k (ground truth)
+        for t in range(U):
+            L.pecnn_forward(plan, self.model, S[-2], S[-1], pred[t])
+            S.append(pred[t])
+        self.loss.zero_()
+        grads.zero_()
+        for t in range(U):
+            # l_8: mean over the unrolled frames; l_1: the first frame once more
+            w = 1.0 / U + (one_step_weight if t == 0 else 0.0)
+            L.pecnn_loss_mse(plan, pred[t], wb.buf[t + 2], sx, sv, w, n_free, self.loss, grads[t], ws=self.ws_r)
+        self.g.zero_()
+        for t in range(U - 1, -1, -1):
+            # pred[t] = f(S[t], S[t+1]); S[t+2] = pred[t]; only predicted frames carry gradients
+            g_cur = grads[t - 1] if t >= 1 else None
+            g_prev = grads[t - 2] if t >= 2 else None
+            L.pecnn_backward(plan, self.model, S[t], S[t + 1], grads[t], g_cur, g_prev, self.g, ws=self.ws_b)
+        self.t += 1
+        L.pecnn_adam_step(self.theta, self.m, self.v, self.g, self.t, lr=self.lr if lr is None else lr)
+        return self.loss
+
+
+def eval_loss(tr: Trainer, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0):
+    """The training loss of the current theta on the windows already gathered in wb (no update)."""
+    import torch
+    from . import _lib as L
+    U = wb.n_unroll
+    N = wb.n_win * wb.npw
+    pred = torch.empty(U, 6, N, device=tr.device)
+    S = [wb.buf[0], wb.buf[1]]
+    loss = torch.zeros(1, dtype=torch.float64, device=tr.device)
+    ws_r = plan.workspace(L.WS_REDUCE)
+    for t in range(U):
+        L.pecnn_forward(plan, tr.model, S[-2], S[-1], pred[t])
+        S.append(pred[t])
+        w = 1.0 / U + (one_step_weight if t == 0 else 0.0)
+        L.pecnn_loss_mse(plan, pred[t], wb.buf[t + 2], sx, sv, w, n_free, loss, None, ws=ws_r)
+    return float(loss.item())
+
+
+def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0, dt_nn=5e-3, device="cuda"):
+    """Network rollout of n_frames from frame 0 (S^{-1} = S^0) of the given scenes; position RMS
+    against the saved simulator frame n_frames, per scene, divided by the cloth width (FP64
+    reduction kernel)."""
+    import torch
+    from . import _lib as L
+    sc = [traj.scenes[int(b)] for b in scene_ids]
+    batch = I.make_batch(sc)
+    plan = L.Plan.from_batch(batch, device)
+    th = torch.tensor(np.asarray(theta, np.float32), device=device)
+    model = L.make_model(th, ch, precision, dt=dt_nn)
+    idx = np.concatenate([np.arange(traj.batch.node_off[b], traj.batch.node_off[b + 1]) for b in scene_ids])
+    idx_t = torch.tensor(idx, device=device)
+    s0 = traj.frames[0][:, idx_t].contiguous()
+    ref = traj.frames[n_frames][:, idx_t].contiguous()
+    a, b = s0.clone(), s0.clone()
+    g = L.Guard()
+    g.stretch_max, g.energy_gain_max, g.check_every, g.substeps = 1e9, 1e30, 0, traj.stride
+    fb = torch.zeros(batch.n, dtype=torch.int32, device=device)
+    L.pecnn_rollout(plan, model, traj.sim, g, a, b, n_frames, fb, None)
+    out = torch.zeros(4 * batch.n, dtype=torch.float64, device=device)
+    L.cloth_reduce_fp64(plan, traj.sim, b, ref, out)
+    torch.cuda.synchronize()
+    r = out.cpu().numpy().reshape(-1, 4)
+    width = (batch.W - 1) * batch.h
+    rms = np.sqrt(r[:, 0] / (batch.H * batch.W)) / width
+    return rms, b
+
+
+def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=32, lr=1e-3, seed=4,
+          n_frames=201, stride=10, log_every=500, eval_frames=100, device="cuda", verbose=True, lr_final=None):
+    """Adam at lr, annealed along a cosine to lr_final over the run when lr_final is given (the
+    post-process cosine schedule of Table 1)."""
+    import torch
+    mat = I.Material()
+    t0 = time.time()
+    scenes = I.random_scenes([(size, size)] * n_scenes, seed=seed)
+    traj = Trajectories(scenes, mat, n_frames, stride, device)
+    sx, sv = traj.increment_scales()
+    t_gen = time.time() - t0
+    train_ids = list(range(n_scenes - n_val))
+    val_ids = list(range(n_scenes - n_val, n_scenes))
+    wb = WindowBatch(traj, train_ids, n_win, n_unroll, device)
+    tr = Trainer(ch=ch, dt_nn=stride * mat.dt, lr=lr, device=device)
+    theta0 = tr.theta.cpu().numpy().copy()
+    rng = np.random.default_rng(seed)
+    # fixed held-out windows for a deterministic validation loss
+    wv = WindowBatch(traj, val_ids, n_win, n_unroll, device)
+    val_plan, val_free = wv.sample(np.random.default_rng(seed + 1))
+    curve = []
+    t1 = time.time()
+    best = (math.inf, theta0)
+    for it in range(1, iters + 1):
+        plan, n_free = wb.sample(rng)
+        lr_t = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (it - 1) / iters))
+        loss = tr.step(wb, plan, n_free, sx, sv, lr=lr_t)
+        if it % log_every == 0 or it == 1 or it == iters:
+            lv = float(loss.item())
+            vl = eval_loss(tr, wv, val_plan, val_free, sx, sv)
+            curve.append((it, lv, vl))
+            if not np.isfinite(lv):
+                raise FloatingPointError("training diverged at iteration %d" % it)
+            rms_v, _ = rollout_rms(traj, val_ids, tr.theta.cpu().numpy(), ch, eval_frames, dt_nn=stride * mat.dt,
+                                   device=device)
+            if rms_v.mean() < best[0]:
+                best = (float(rms_v.mean()), tr.theta.cpu().numpy().copy())
+            if verbose:
+                print("iter %6d loss %.5g  val loss %.5g  val rms@%d %.4g  (%.1f s)" % (
+                    it, lv, vl, eval_frames, rms_v.mean(), time.time() - t1), flush=True)
+        plan.close()
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    theta_best = best[1]
+    rms_trained, _ = rollout_rms(traj, val_ids, theta_best, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
+    rms_untrained, _ = rollout_rms(traj, val_ids, theta0, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
+    tr.theta.copy_(torch.tensor(theta_best, device=device))
+    val_loss_best = eval_loss(tr, wv, val_plan, val_free, sx, sv)
+    report = {
+        "scenes": n_scenes, "grid": size, "val_scenes": n_val, "iters": iters, "minibatch": n_win,
+        "unroll": n_unroll, "channels": ch, "lr": lr, "lr_final": lr_final, "stride": stride, "frames": n_frames,
+        "increment_scales": [sx, sv], "loss_curve": curve, "generation_s": t_gen, "train_s": t_train,
+        "val_rms_trained": rms_trained.tolist(), "val_rms_untrained": rms_untrained.tolist(),
+        "val_rms_trained_mean": float(rms_trained.mean()), "val_rms_untrained_mean": float(rms_untrained.mean()),
+        "eval_frames": eval_frames, "val_loss_first": curve[0][2], "val_loss_best_theta": val_loss_best,
+    }
+    return theta_best, report
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--scenes", type=int, default=64)
+    ap.add_argument("--size", type=int, default=64)
+    ap.add_argument("--val", type=int, default=8)
+    ap.add_argument("--iters", type=int, default=20000)
+    ap.add_argument("--minibatch", type=int, default=32)
+    ap.add_argument("--unroll", type=int, default=8)
+    ap.add_argument("--ch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=None)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--log-every", type=int, default=500)
+    ap.add_argument("--out", default=os.path.join(HERE, "weights", "pecnn_ch32.npy"))
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args()
+    theta, report = train(args.scenes, args.size, args.val, args.iters, args.minibatch, args.unroll, args.ch,
+                          args.lr, args.seed, log_every=args.log_every, lr_final=args.lr_final)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    np.save(args.out, theta.astype(np.float32), allow_pickle=False)
+    rep = args.report or os.path.splitext(args.out)[0] + "_report.json"
+    with open(rep, "w") as f:
+        json.dump(report, f, indent=1)
+    print(json.dumps({k: v for k, v in report.items() if k != "loss_curve"}))
+
+
+if __name__ == "__main__":
+    main()

@@ -161,7 +161,7 @@ def _dv_from_state(batch, s1, out, dt):
 
 
 @pytest.mark.parametrize("ch", [16, 32])
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 def test_cnn_forward_fp32_matches_oracle(torch_mod, L, ch, cfg):
     batch, s0, s1, th = _cnn_inputs(ragged_sizes(), 200 + ch, ch, 30.0)
     got = _cnn_gpu(L, torch_mod, batch, s0, s1, th, ch, L.PECNN_FP32, cfg=cfg)
@@ -199,7 +199,7 @@ def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch):
 def test_cnn_tile_configs_bitwise_equal(torch_mod, L):
     for prec in (0, 1):
         batch, s0, s1, th = _cnn_inputs(ragged_sizes(), 400, 32, 10.0)
-        outs = [_cnn_gpu(L, torch_mod, batch, s0, s1, th, 32, prec, cfg=c) for c in range(3)]
+        outs = [_cnn_gpu(L, torch_mod, batch, s0, s1, th, 32, prec, cfg=c) for c in range(4)]
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
 
