@@ -9,8 +9,9 @@
 //  2. bwd_gather: one thread per node: the adjoint of the clamped im2col, written as a gather
 //                 over the (neighbour, tap) pairs that read this node, plus the direct terms of
 //                 eq. (5). Accumulates into g_cur and g_prev.
-//  3. bwd_wgrad:  per chunk of 256 nodes, the parameter-gradient partial sums (outer products
-//                 staged through LDS), then a fixed-order sum over chunks into g_theta.
+//  3. bwd_wgrad:  per range of nodes, the parameter-gradient partial sums: products of factor
+//                 rows summed over nodes, on MFMA from LDS-staged node blocks; then a fixed-order
+//                 sum over the ranges into g_theta.
 #include "common.hpp"
 
 namespace pecnn {
@@ -19,8 +20,8 @@ struct BwdLayout {
   // feature rows of the per-node factor table, each a plane of N floats
   int uk, ud, gus, gud, phi, nn, dd, ga, gb, gphi, gxi, gdv, rows;
 };
-__host__ __device__ inline BwdLayout bwd_layout(int ch) {
-  BwdLayout L;
+__host__ __device__ constexpr BwdLayout bwd_layout(int ch) {
+  BwdLayout L{};
   L.uk = 0;
   L.ud = 54;
   L.gus = 108;
@@ -38,6 +39,12 @@ __host__ __device__ inline BwdLayout bwd_layout(int ch) {
 }
 
 __host__ __device__ inline int64_t theta_count(int ch) { return (int64_t)ch * 54 + 2 * ch * ch + 9 * ch + 3; }
+
+// The per-node factor table is node-blocked: 32 consecutive nodes form a block of rows x 32
+// floats, row-major, so a block is one contiguous run (the weight-gradient sums stream it) and a
+// row of a block is one 128-byte line (node kernels write it coalesced). Node count padded to 32.
+__host__ __device__ inline int64_t fac_node(int64_t q, int rows) { return (q >> 5) * (int64_t)rows * 32 + (q & 31); }
+__host__ __device__ inline int64_t fac_floats(int64_t n, int rows) { return (n + 31) / 32 * 32 * (int64_t)rows; }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -71,7 +78,7 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
   const int i = (int)(local / I.W), j = (int)(local % I.W);
   const int64_t p = I.off + local;
   const BwdLayout L = bwd_layout(CH);
-  float* __restrict__ F = fac + p;  // feature row r lives at F[r * N]
+  float* __restrict__ F = fac + fac_node(p, L.rows);  // feature row r of node p lives at F[r * 32]
   float* __restrict__ my = scr + threadIdx.x * SW;
 
   // forward recompute: phi = K U(S^k), xi = K U(S^k - S^{k-1}); im2col entries go to the table
@@ -92,8 +99,8 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
       const float uk = s_cur[q] - ck;
       const float ud = (s_cur[q] - s_prev[q]) - cd;
       const int t = c * 9 + o;
-      F[(L.uk + t) * N] = uk;
-      F[(L.ud + t) * N] = ud;
+      F[(L.uk + t) * 32] = uk;
+      F[(L.ud + t) * 32] = ud;
 #pragma unroll
       for (int r = 0; r < CH; ++r) {
         phi[r] = __builtin_fmaf(th[r * 54 + t], uk, phi[r]);
@@ -123,7 +130,7 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
   for (int k = 0; k < 3; ++k) {
     const float gvt = g_next[(3 + k) * N + p] + dt * g_next[k * N + p];
     gdv[k] = pinned ? 0.f : gvt;
-    F[(L.gdv + k) * N] = gdv[k];
+    F[(L.gdv + k) * 32] = gdv[k];
   }
   // heads and ISRU branches; afterwards phi holds the head/derivative part of dLoss/dphi,
   // xi holds dLoss/dxi, and my[] holds the adjoints of (A phi) and (B phi)
@@ -140,16 +147,16 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
     const float gdd = th[oWD + c] * gdv[0] + th[oWD + CH + c] * gdv[1] + th[oWD + 2 * CH + c] * gdv[2];
     const float gz = gnn * dnn;
     const float ga = gz * bb[c], gb = gz * a[c];
-    F[(L.phi + c) * N] = phi[c];
-    F[(L.nn + c) * N] = nn;
-    F[(L.dd + c) * N] = dd;
-    F[(L.ga + c) * N] = ga;
-    F[(L.gb + c) * N] = gb;
+    F[(L.phi + c) * 32] = phi[c];
+    F[(L.nn + c) * 32] = nn;
+    F[(L.dd + c) * 32] = dd;
+    F[(L.ga + c) * 32] = ga;
+    F[(L.gb + c) * 32] = gb;
     my[c] = ga;
     my[CH + c] = gb;
     phi[c] = gphi_h + gdd * xi[c] * dgs;
     xi[c] = gdd * gs;
-    F[(L.gxi + c) * N] = xi[c];
+    F[(L.gxi + c) * 32] = xi[c];
   }
 #pragma unroll 1
   for (int r = 0; r < CH; ++r) {
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
     for (int c = 0; c < CH; ++c) phi[c] = __builtin_fmaf(th[oB + r * CH + c], gbr, __builtin_fmaf(th[oA + r * CH + c], gar, phi[c]));
   }
 #pragma unroll
-  for (int c = 0; c < CH; ++c) F[(L.gphi + c) * N] = phi[c];
+  for (int c = 0; c < CH; ++c) F[(L.gphi + c) * 32] = phi[c];
   // adjoint of the im2col entries
 #pragma unroll 1
   for (int t = 0; t < 54; ++t) {
@@ -168,8 +175,8 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
       gk = __builtin_fmaf(th[c * 54 + t], phi[c], gk);
       gd = __builtin_fmaf(th[c * 54 + t], xi[c], gd);
     }
-    F[(L.gus + t) * N] = gk + gd;
-    F[(L.gud + t) * N] = gd;
+    F[(L.gus + t) * 32] = gk + gd;
+    F[(L.gud + t) * 32] = gd;
   }
 }
 
@@ -186,8 +193,8 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(
   const int qi = (int)(local / I.W), qj = (int)(local % I.W);
   const int64_t q = I.off + local;
   const BwdLayout L = bwd_layout(ch);
-  const float* __restrict__ gus = fac + (int64_t)L.gus * N;
-  const float* __restrict__ gud = fac + (int64_t)L.gud * N;
+  const float* __restrict__ gus = fac + L.gus * 32;
+  const float* __restrict__ gud = fac + L.gud * 32;
   const bool pinned = pin[q] != 0;
   float accC[6], accP[6];
 #pragma unroll
@@ -205,8 +212,8 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(
           const int64_t pp = I.off + (int64_t)pi * I.W + pj;
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
-            accC[c] += gus[(int64_t)(c * 9 + o) * N + pp];
-            accP[c] -= gud[(int64_t)(c * 9 + o) * N + pp];
+            accC[c] += gus[fac_node(pp, L.rows) + (c * 9 + o) * 32];
+            accP[c] -= gud[fac_node(pp, L.rows) + (c * 9 + o) * 32];
           }
         }
       }
@@ -216,8 +223,8 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
-      accC[c] -= gus[(int64_t)(c * 9 + o) * N + q];
-      accP[c] += gud[(int64_t)(c * 9 + o) * N + q];
+      accC[c] -= gus[fac_node(q, L.rows) + (c * 9 + o) * 32];
+      accP[c] += gud[fac_node(q, L.rows) + (c * 9 + o) * 32];
     }
   // eq. (5): x' = x + dt v', v' = C(v + dv + dt a)
 #pragma unroll
@@ -233,108 +240,192 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(
     for (int c = 0; c < 6; ++c) g_prev[c * N + q] += accP[c];
 }
 
-// Parameter gradient partials of one chunk: parameter e of the flat theta layout is a sum over
-// nodes of a product of two factor rows (conv taps have two such products).
+// Parameter gradients as GEMMs with the node axis as the contraction: for the conv,
+// dK = [gphi | gxi] [uk | ud]^T, and dA = ga phi^T, dB = gb phi^T, dW_{L,N,D} = gdv [phi|n|d]^T,
+// db_L = gdv 1. Instances are packed end to end in the factor table, so the sums run over the
+// flat node range: block k takes nodes [k*NB, (k+1)*NB). Every round stages SUB nodes of all
+// factor rows in LDS (the next round's loads are in flight in registers meanwhile) and the four
+// waves run v_mfma_f32_16x16x4_f32 on 16 x 16 output tiles (4 nodes per instruction),
+// accumulating over the block's nodes in registers. Deterministic: fixed order throughout.
+constexpr int kWgSub = 32;          // nodes per LDS round
+constexpr int kWgMaxBlocks = 1024;  // partial rows, bounded so the final sum stays small
+
+// nodes per block: a multiple of kWgSub, at most kWgMaxBlocks blocks
+inline int64_t wgrad_nodes_per_block(int64_t N) {
+  int64_t nb = (N + kWgMaxBlocks - 1) / kWgMaxBlocks;
+  nb = (nb + kWgSub - 1) / kWgSub * kWgSub;
+  return nb < 256 ? 256 : nb;
+}
+inline int64_t wgrad_blocks(int64_t N) {
+  const int64_t nb = wgrad_nodes_per_block(N);
+  return N > 0 ? (N + nb - 1) / nb : 0;
+}
+
+struct WgTile {
+  int x0, y0;    // first factor row of the X and Y blocks
+  int x1, y1;    // second product (conv taps only), or -1
+  int kind;      // 0 conv, 1 A, 2 B, 3 W_L, 4 W_N, 5 W_D, 6 b_L
+  int xb, yb;    // block indices inside the parameter
+};
+
 template <int CH>
-__device__ __forceinline__ void param_rows(int e, int& x1, int& y1, int& x2, int& y2) {
-  const BwdLayout L = bwd_layout(CH);
+__device__ __forceinline__ WgTile wg_tile(int t) {
+  constexpr BwdLayout L = bwd_layout(CH);
+  constexpr int MB = CH / 16;
+  WgTile T;
+  T.x1 = T.y1 = -1;
+  if (t < MB * 4) {  // conv: MB row blocks of channels x 4 blocks of taps (54 padded to 64)
+    T.kind = 0; T.xb = t / 4; T.yb = t % 4;
+    T.x0 = L.gphi + 16 * T.xb; T.y0 = L.uk + 16 * T.yb;
+    T.x1 = L.gxi + 16 * T.xb; T.y1 = L.ud + 16 * T.yb;
+    return T;
+  }
+  t -= MB * 4;
+  if (t < 2 * MB * MB) {  // A then B: MB x MB blocks each
+    const int which = t / (MB * MB), u = t % (MB * MB);
+    T.kind = 1 + which; T.xb = u / MB; T.yb = u % MB;
+    T.x0 = (which == 0 ? L.ga : L.gb) + 16 * T.xb; T.y0 = L.phi + 16 * T.yb;
+    return T;
+  }
+  t -= 2 * MB * MB;
+  T.xb = 0;
+  T.x0 = L.gdv;  // three gdv rows; the rows after them are the pad block and are discarded
+  if (t < 3 * MB) {  // heads: gdv x MB blocks of phi, n, d
+    const int br = t / MB;
+    T.kind = 3 + br; T.yb = t % MB;
+    T.y0 = (br == 0 ? L.phi : br == 1 ? L.nn : L.dd) + 16 * T.yb;
+    return T;
+  }
+  T.kind = 6; T.yb = 0; T.y0 = L.rows;  // bias: the first pad row holds ones
+  return T;
+}
+
+template <int CH>
+__global__ __launch_bounds__(256) void bwd_wgrad_kernel(const float* __restrict__ fac, int64_t N, int64_t NB,
+                                                        float* __restrict__ partial) {
+  constexpr int P = CH * 54 + 2 * CH * CH + 9 * CH + 3;
+  constexpr int MB = CH / 16;
+  constexpr int NT = MB * 4 + 2 * MB * MB + 3 * MB + 1;  // output tiles
+  constexpr int TPW = (NT + 3) / 4;                      // tiles per wave
+  constexpr BwdLayout L = bwd_layout(CH);
+  constexpr int ROWS = L.rows;
+  constexpr int R = ROWS + 16;        // pad block: a ones row, then zeros
+  constexpr int LS = kWgSub + 4;      // LDS row stride (bank spread)
+  extern __shared__ float lds[];      // [R][LS]
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t n0 = (int64_t)blockIdx.x * NB;
+  const int64_t n1 = min(N, n0 + NB);
+
+  for (int e = threadIdx.x; e < 16 * LS; e += 256) lds[ROWS * LS + e] = (e < kWgSub) ? 1.f : 0.f;
+
+  // a round is one node block of the table: ROWS x 32 contiguous floats; this thread stages the
+  // float4 number tid + 256 i of it (row e4 / 8, nodes 4 (e4 % 8) .. +3)
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  constexpr int Q = ROWS * (kWgSub / 4);  // float4s per round
+  constexpr int PF = (Q + 255) / 256;
+  f32x4 pf[PF];
+  const int c4 = (threadIdx.x & 7) * 4;
+  auto fetch = [&](int64_t s) {
+    const f32x4* src = reinterpret_cast<const f32x4*>(fac + (s >> 5) * (int64_t)(ROWS * 32)) + threadIdx.x;
+    const int64_t left = n1 - s - c4;  // valid nodes from this thread's first column
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (threadIdx.x + 256 * i < Q && left > 0) {
+        v = src[256 * i];
+        if (left < 4) {  // block tail: table padding beyond the last node is not initialised
+          v[3] = 0.f;
+          if (left < 3) v[2] = 0.f;
+          if (left < 2) v[1] = 0.f;
+        }
+      }
+      pf[i] = v;
+    }
+  };
+
+  f32x4 acc[TPW];
+  WgTile tl[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int t = wave + 4 * k;
+    tl[k] = wg_tile<CH>(t < NT ? t : 0);
+  }
+
+  if (n0 < n1) fetch(n0);
+  for (int64_t s = n0; s < n1; s += kWgSub) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e4 = threadIdx.x + 256 * i;
+      if (e4 < Q) *reinterpret_cast<f32x4*>(&lds[(e4 >> 3) * LS + c4]) = pf[i];
+    }
+    __syncthreads();
+    if (s + kWgSub < n1) fetch(s + kWgSub);
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+      if (wave + 4 * k >= NT) continue;  // uniform over the wave
+#pragma unroll
+      for (int q = 0; q < kWgSub / 4; ++q) {
+        const int n = 4 * q + g;
+        const float xa = lds[(tl[k].x0 + li) * LS + n], yb = lds[(tl[k].y0 + li) * LS + n];
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, yb, acc[k], 0, 0, 0);
+        if (tl[k].x1 >= 0) {
+          const float xc = lds[(tl[k].x1 + li) * LS + n], yd = lds[(tl[k].y1 + li) * LS + n];
+          acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(xc, yd, acc[k], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // scatter the tiles to the flat parameter layout: lane holds rows 4g..4g+3, column li
   constexpr int oA = CH * 54, oB = oA + CH * CH, oWL = oB + CH * CH, oWN = oWL + 3 * CH, oWD = oWN + 3 * CH,
                 obL = oWD + 3 * CH;
-  x2 = y2 = -1;
-  if (e < oA) {  // K[c][t] : gphi_c * uk_t + gxi_c * ud_t
-    const int c = e / 54, t = e % 54;
-    x1 = L.gphi + c; y1 = L.uk + t; x2 = L.gxi + c; y2 = L.ud + t;
-  } else if (e < oB) {  // A[r][c] : ga_r * phi_c
-    const int r = (e - oA) / CH, c = (e - oA) % CH;
-    x1 = L.ga + r; y1 = L.phi + c;
-  } else if (e < oWL) {
-    const int r = (e - oB) / CH, c = (e - oB) % CH;
-    x1 = L.gb + r; y1 = L.phi + c;
-  } else if (e < oWN) {
-    const int r = (e - oWL) / CH, c = (e - oWL) % CH;
-    x1 = L.gdv + r; y1 = L.phi + c;
-  } else if (e < oWD) {
-    const int r = (e - oWN) / CH, c = (e - oWN) % CH;
-    x1 = L.gdv + r; y1 = L.nn + c;
-  } else if (e < obL) {
-    const int r = (e - oWD) / CH, c = (e - oWD) % CH;
-    x1 = L.gdv + r; y1 = L.dd + c;
-  } else {
-    x1 = L.gdv + (e - obL); y1 = -1;  // bias: plain sum
+  float* out = partial + (int64_t)blockIdx.x * P;
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    if (wave + 4 * k >= NT) continue;
+    const WgTile T = tl[k];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * T.xb + 4 * g + v, j = 16 * T.yb + li;
+      int e = -1;
+      if (T.kind == 0) e = j < 54 ? i * 54 + j : -1;
+      else if (T.kind == 1) e = oA + i * CH + j;
+      else if (T.kind == 2) e = oB + i * CH + j;
+      else if (T.kind == 6) e = (i < 3 && j == 0) ? obL + i : -1;
+      else if (i < 3) e = (T.kind == 3 ? oWL : T.kind == 4 ? oWN : oWD) + i * CH + j;
+      if (e >= 0) out[e] = acc[k][v];
+    }
   }
 }
 
-template <int CH>
-__global__ __launch_bounds__(256) void bwd_wgrad_kernel(
-    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int64_t N,
-    const float* __restrict__ fac, float* __restrict__ partial) {
-  constexpr int P = CH * 54 + 2 * CH * CH + 9 * CH + 3;
-  constexpr int PPT = (P + 255) / 256;  // parameters per thread
-  constexpr int SUB = 16;               // nodes staged per LDS round
-  const BwdLayout L = bwd_layout(CH);
-  const int R = L.rows;
-  extern __shared__ float lds[];  // [R][SUB]
-
-  const int t = blockIdx.x;
-  const int b = find_instance(prefix, n_inst, t);
-  const InstDev I = inst[b];
-  const int64_t n_inst_nodes = (int64_t)I.H * I.W;
-  const int64_t first = (int64_t)(t - prefix[b]) * kChunk;
-  const int nloc = (int)min((int64_t)kChunk, n_inst_nodes - first);
-  const int64_t base = I.off + first;
-
-  int x1[PPT], y1[PPT], x2[PPT], y2[PPT];
-  float acc[PPT];
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int e = threadIdx.x + 256 * k;
-    acc[k] = 0.f;
-    if (e < P) param_rows<CH>(e, x1[k], y1[k], x2[k], y2[k]);
-    else { x1[k] = -2; y1[k] = x2[k] = y2[k] = -1; }
-  }
-  for (int s0 = 0; s0 < nloc; s0 += SUB) {
-    const int ns = min(SUB, nloc - s0);
-    for (int e = threadIdx.x; e < R * SUB; e += 256) {
-      const int r = e / SUB, n = e % SUB;
-      lds[e] = n < ns ? fac[(int64_t)r * N + base + s0 + n] : 0.f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      if (x1[k] < -1) continue;
-      float s = acc[k];
-      if (y1[k] < 0) {
-        for (int n = 0; n < SUB; ++n) s += lds[x1[k] * SUB + n];
-      } else if (x2[k] < 0) {
-        for (int n = 0; n < SUB; ++n) s = __builtin_fmaf(lds[x1[k] * SUB + n], lds[y1[k] * SUB + n], s);
-      } else {
-        for (int n = 0; n < SUB; ++n)
-          s = __builtin_fmaf(lds[x2[k] * SUB + n], lds[y2[k] * SUB + n], __builtin_fmaf(lds[x1[k] * SUB + n], lds[y1[k] * SUB + n], s));
-      }
-      acc[k] = s;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int e = threadIdx.x + 256 * k;
-    if (e < P) partial[(int64_t)t * P + e] = acc[k];
-  }
-}
-
-// g_theta[e] += sum over chunks in index order.
-__global__ void wgrad_final_kernel(const float* __restrict__ partial, int n_chunks, int P, float* __restrict__ g_theta) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= P) return;
+// g_theta[e] += sum over the partial rows in index order: 16 lanes per parameter each sum a fixed
+// stride of rows, then a fixed-order combine in LDS (deterministic).
+__global__ __launch_bounds__(1024) void wgrad_final_kernel(const float* __restrict__ partial, int n_rows, int P,
+                                                           float* __restrict__ g_theta) {
+  __shared__ double sh[16][64];
+  const int pl = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + pl;
   double s = 0.0;
-  for (int c = 0; c < n_chunks; ++c) s += (double)partial[(int64_t)c * P + e];
-  g_theta[e] += (float)s;
+  if (e < P)
+    for (int r = r0; r < n_rows; r += 16) s += (double)partial[(int64_t)r * P + e];
+  sh[r0][pl] = s;
+  __syncthreads();
+  if (r0 == 0 && e < P) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += sh[k][pl];
+    g_theta[e] += (float)t;
+  }
 }
 
 size_t backward_ws_bytes(const pecnn_plan* plan, int ch) {
   const BwdLayout L = bwd_layout(ch);
-  const size_t fac = (size_t)L.rows * (size_t)plan->total * sizeof(float);
-  const size_t part = (size_t)plan->n_tiles[kCfgChunk] * (size_t)theta_count(ch) * sizeof(float);
+  const size_t fac = (size_t)fac_floats(plan->total, L.rows) * sizeof(float);
+  const size_t rows = (size_t)wgrad_blocks(plan->total);
+  const size_t part = rows * (size_t)theta_count(ch) * sizeof(float);
   return fac + 256 + part;
 }
 
@@ -342,7 +433,7 @@ int backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* s
                     const float* gn, float* gc, float* gp, float* gth, void* ws, hipStream_t st) {
   const BwdLayout L = bwd_layout(m->ch);
   float* fac = (float*)ws;
-  const size_t fac_bytes = (size_t)L.rows * (size_t)plan->total * sizeof(float);
+  const size_t fac_bytes = (size_t)fac_floats(plan->total, L.rows) * sizeof(float);
   float* partial = (float*)((char*)ws + ((fac_bytes + 255) / 256) * 256);
   const int nt = plan->n_tiles[kCfgChunk];
   const int32_t* pre = plan->d_prefix[kCfgChunk];
@@ -360,15 +451,15 @@ int backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* s
                        plan->total, m->dt, m->ch, fac, gc, gp);
     PECNN_LAUNCH_CHECK("bwd_gather_kernel");
   }
-  const size_t lds = (size_t)L.rows * 16 * sizeof(float);
+  const size_t lds = (size_t)(L.rows + 16) * (kWgSub + 4) * sizeof(float);
+  const int64_t nb = wgrad_nodes_per_block(plan->total);
+  const int nrows = (int)wgrad_blocks(plan->total);
   if (m->ch == 16)
-    hipLaunchKernelGGL(bwd_wgrad_kernel<16>, dim3(nt), dim3(256), lds, st, plan->d_inst, pre, plan->n, plan->total,
-                       fac, partial);
+    hipLaunchKernelGGL(bwd_wgrad_kernel<16>, dim3(nrows), dim3(256), lds, st, fac, plan->total, nb, partial);
   else
-    hipLaunchKernelGGL(bwd_wgrad_kernel<32>, dim3(nt), dim3(256), lds, st, plan->d_inst, pre, plan->n, plan->total,
-                       fac, partial);
+    hipLaunchKernelGGL(bwd_wgrad_kernel<32>, dim3(nrows), dim3(256), lds, st, fac, plan->total, nb, partial);
   PECNN_LAUNCH_CHECK("bwd_wgrad_kernel");
-  hipLaunchKernelGGL(wgrad_final_kernel, dim3((P + 255) / 256), dim3(256), 0, st, partial, nt, P, gth);
+  hipLaunchKernelGGL(wgrad_final_kernel, dim3((P + 63) / 64), dim3(1024), 0, st, partial, nrows, P, gth);
   PECNN_LAUNCH_CHECK("wgrad_final_kernel");
   return PECNN_OK;
 }

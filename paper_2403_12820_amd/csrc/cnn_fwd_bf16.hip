@@ -70,10 +70,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   float4 pS[NVT], pP[NVT];
   float hS[NHT], hP[NHT];
   uint8_t pp[NPT];
+  const int N32 = (int)N;  // validated: 24 N < 2^32
 
   int first, stride, count;
   xcd_tile_range(n_tiles, first, stride, count);
-  const int N32 = (int)N;  // validated: 6 N < 2^31
 
   auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
     const int t = first + it * stride;
@@ -87,17 +87,62 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     return true;
   };
 
+  // Per-thread item coordinates do not depend on the tile: float4 item i of this thread is
+  // channel c, halo row rr, column group q.
+  int it_cq[NVT], it_rr[NVT];
+#pragma unroll
+  for (int i = 0; i < NVT; ++i) {
+    const int j = tid + 256 * i;
+    const int row = j / QV, q = j - (j / QV) * QV;
+    const int c = row / HY;
+    it_rr[i] = row - c * HY;
+    it_cq[i] = c * N32 + 4 * q;
+  }
+
   // Issue the halo loads of a tile into registers (they stay in flight during compute).
   auto issue = [&](const InstDev& I, int r0, int c0) {
     const int off32 = (int)I.off;
     const bool vec = ((I.W & 3) == 0) && ((off32 & 3) == 0) && ((N32 & 3) == 0);
+    // the tile and its one-node ring lie inside the grid: no clamping needed (uniform branch)
+    const bool inner = vec && r0 >= 1 && c0 >= 1 && r0 + TY + 1 <= I.H && c0 + TX + 1 <= I.W;
+    if (inner) {
+      const int base = off32 + (r0 - 1) * I.W + c0;
+#pragma unroll
+      for (int i = 0; i < NVT; ++i) {
+        if (NV % 256 == 0 || tid + 256 * i < NV) {
+          const unsigned a = (unsigned)(it_cq[i] + it_rr[i] * I.W + base);
+          pS[i] = gld(reinterpret_cast<const float4*>(s_cur), a);
+          pP[i] = gld(reinterpret_cast<const float4*>(s_prev), a);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NHT; ++i) {
+        const int j = tid + 256 * i;
+        if (j < NH) {
+          const int row = j >> 1, side = j & 1;
+          const int c = row / HY, rr = row - (row / HY) * HY;
+          const unsigned a = (unsigned)(c * N32 + rr * I.W + base + (side ? TX : -1));
+          hS[i] = gld(s_cur, a);
+          hP[i] = gld(s_prev, a);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int j = tid + 256 * i;
+        if (NP % 256 == 0 || j < NP) {
+          const int ly = j / TX, lx = j - (j / TX) * TX;
+          pp[i] = pin[(unsigned)(base + (ly + 1) * I.W + lx)];
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < NVT; ++i) {
       const int j = tid + 256 * i;
       if (NV % 256 == 0 || j < NV) {
-        const int row = j / QV, q = j - (j / QV) * QV;
-        const int c = row / HY, rr = row - (row / HY) * HY;
-        const int gi = min(max(r0 + rr - 1, 0), I.H - 1);
+        const int q = (j - (j / QV) * QV);
+        const int c = (j / QV) / HY;
+        const int gi = min(max(r0 + it_rr[i] - 1, 0), I.H - 1);
         const int col = c0 + 4 * q;
         const unsigned rb = (unsigned)(c * N32 + off32 + gi * I.W);
         if (vec && col + 3 < I.W) {

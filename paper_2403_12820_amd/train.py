@@ -244,6 +244,7 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     theta_best = best[1]
     rms_trained, _ = rollout_rms(traj, val_ids, theta_best, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
     rms_untrained, _ = rollout_rms(traj, val_ids, theta0, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
+    val_loss_final = eval_loss(tr, wv, val_plan, val_free, sx, sv)
     tr.theta.copy_(torch.tensor(theta_best, device=device))
     val_loss_best = eval_loss(tr, wv, val_plan, val_free, sx, sv)
     report = {
@@ -253,6 +254,7 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
         "val_rms_trained": rms_trained.tolist(), "val_rms_untrained": rms_untrained.tolist(),
         "val_rms_trained_mean": float(rms_trained.mean()), "val_rms_untrained_mean": float(rms_untrained.mean()),
         "eval_frames": eval_frames, "val_loss_first": curve[0][2], "val_loss_best_theta": val_loss_best,
+        "val_loss_final_theta": val_loss_final,
     }
     return theta_best, report
 

@@ -98,8 +98,8 @@ def test_training_reduces_loss_and_beats_untrained(L):
     from paper_2403_12820_amd.train import train
     theta, rep = train(n_scenes=12, size=24, n_val=3, iters=600, n_win=8, n_unroll=4, ch=16, lr=1e-3,
                        seed=3, n_frames=41, stride=10, log_every=200, eval_frames=20, verbose=False, lr_final=1e-4)
-    # held-out windows: the loss of the kept parameters is below the initial one, and so is the
-    # rollout error of held-out scenes
-    assert rep["val_loss_best_theta"] < rep["val_loss_first"], rep["loss_curve"]
+    # held-out windows: the loss of the final parameters is below the initial one, and the kept
+    # parameters' rollout error on held-out scenes is below the untrained network's
+    assert rep["val_loss_final_theta"] < rep["val_loss_first"], rep["loss_curve"]
     assert rep["val_rms_trained_mean"] < rep["val_rms_untrained_mean"], rep
     assert np.all(np.isfinite(theta))
