@@ -1,11 +1,12 @@
-"""Accuracy of the learned rollout at 256 x 256 (precision study), through the C ABI.
+"""Accuracy of the learned rollout (precision study), through the C ABI.
 
-For each scene: a 100-frame network rollout in bf16 and in FP32 operands, against the FP32
-mass-spring simulator over the same simulated time (10 steps per frame). Position RMS
-(divided by the cloth width) and energy are FP64 reductions on the GPU (cloth_reduce_fp64).
-The simulator reference itself is held to the FP64 CPU reference by the GPU tests.
+For each scene: a network rollout in bf16 and in FP32 operands, against the FP32 mass-spring
+simulator over the same simulated time (stride simulator steps per network frame). At every
+checkpoint frame, the position RMS (divided by the cloth width), the energy and the maximum
+structural stretch are FP64 reductions on the GPU (cloth_reduce_fp64). The simulator reference
+itself is held to the FP64 CPU reference by the GPU tests.
 
-    python -m paper_2403_12820_amd.evaluate --scenes 2 --frames 100
+    python -m paper_2403_12820_amd.evaluate --scenes 2 --size 256 --checkpoints 1,10,100
 """
 from __future__ import annotations
 
@@ -20,7 +21,8 @@ from . import inputs as I
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def evaluate(theta, size=256, n_scenes=2, frames=100, stride=10, seed=5, ch=32, device="cuda"):
+def evaluate(theta, size=256, n_scenes=2, checkpoints=(1, 2, 5, 10, 20, 50, 100), stride=10, seed=5, ch=32,
+             device="cuda"):
     import torch
     from . import _lib as L
     mat = I.Material()
@@ -30,45 +32,45 @@ def evaluate(theta, size=256, n_scenes=2, frames=100, stride=10, seed=5, ch=32, 
     sim = L.ms_params(mat)
     s0 = torch.tensor(batch.state, device=device)
     th = torch.tensor(np.asarray(theta, np.float32), device=device)
-    out = {}
     red = torch.zeros(4 * batch.n, dtype=torch.float64, device=device)
-
-    # simulator reference over the same simulated time
-    ref_t = torch.empty_like(s0)
-    L.cloth_ms_step(plan, sim, s0, ref_t, frames * stride)
     width = (batch.W - 1) * batch.h
+    nodes = batch.H * batch.W
+    e_ref = nodes * batch.mass * 9.8 * width  # energy scale: the cloth's weight over its width
 
-    def stats(state):
-        L.cloth_reduce_fp64(plan, sim, state, ref_t, red)
+    def reduce(state, ref):
+        L.cloth_reduce_fp64(plan, sim, state, ref, red)
         torch.cuda.synchronize()
-        r = red.cpu().numpy().reshape(-1, 4)
-        return np.sqrt(r[:, 0] / (batch.H * batch.W)) / width, r[:, 1], r[:, 2]
+        return red.cpu().numpy().reshape(-1, 4)
 
-    L.cloth_reduce_fp64(plan, sim, s0, None, red)
-    torch.cuda.synchronize()
-    e0 = red.cpu().numpy().reshape(-1, 4)[:, 1]
-    e_ref = batch.H * batch.W * batch.mass * 9.8 * width
-
-    for name, prec in (("bf16", L.PECNN_BF16), ("fp32", L.PECNN_FP32)):
-        model = L.make_model(th, ch, prec, dt=stride * mat.dt)
-        a, b = s0.clone(), s0.clone()
-        g = L.Guard()
-        g.stretch_max, g.energy_gain_max, g.check_every, g.substeps = 1e9, 1e30, 0, stride
-        fb = torch.zeros(batch.n, dtype=torch.int32, device=device)
-        L.pecnn_rollout(plan, model, sim, g, a, b, frames, fb, None)
-        rms, e, st = stats(b)
-        out[name] = {"rms_width": rms.tolist(), "energy_drift": ((e - e0) / e_ref).tolist(),
-                     "max_structural_stretch": st.tolist()}
-        out[name + "_state"] = b
-    rms, e, st = stats(ref_t)
-    out["ms_fp32"] = {"energy_drift": ((e - e0) / e_ref).tolist(), "max_structural_stretch": st.tolist()}
-    L.cloth_reduce_fp64(plan, sim, out.pop("bf16_state"), out.pop("fp32_state"), red)
-    torch.cuda.synchronize()
-    r = red.cpu().numpy().reshape(-1, 4)
-    out["bf16_vs_fp32_rms_width"] = (np.sqrt(r[:, 0] / (batch.H * batch.W)) / width).tolist()
-    out.update({"scenes": n_scenes, "grid": size, "frames": frames, "stride": stride, "seed": seed,
-                "pins": [sc.pin_kind for sc in scenes]})
-    return out
+    e0 = reduce(s0, None)[:, 1]
+    guard = L.Guard()
+    guard.stretch_max, guard.energy_gain_max, guard.check_every, guard.substeps = 1e9, 1e30, 0, stride
+    runs = {"bf16": L.PECNN_BF16, "fp32": L.PECNN_FP32}
+    models = {k: L.make_model(th, ch, p, dt=stride * mat.dt) for k, p in runs.items()}
+    state = {k: [s0.clone(), s0.clone()] for k in runs}
+    fb = torch.zeros(batch.n, dtype=torch.int32, device=device)
+    ref = [s0.clone(), torch.empty_like(s0)]
+    curve = {k: [] for k in list(runs) + ["ms_fp32", "bf16_vs_fp32"]}
+    done = 0
+    for cp in sorted(set(int(c) for c in checkpoints)):
+        n = cp - done
+        L.cloth_ms_step(plan, sim, ref[0], ref[1], n * stride)
+        ref.reverse()
+        for k in runs:
+            L.pecnn_rollout(plan, models[k], sim, guard, state[k][0], state[k][1], n, fb, None)
+        done = cp
+        for k in runs:
+            r = reduce(state[k][1], ref[0])
+            curve[k].append({"frame": cp, "rms_width": (np.sqrt(r[:, 0] / nodes) / width).tolist(),
+                             "energy_drift": ((r[:, 1] - e0) / e_ref).tolist(),
+                             "max_structural_stretch": r[:, 2].tolist()})
+        r = reduce(ref[0], None)
+        curve["ms_fp32"].append({"frame": cp, "energy_drift": ((r[:, 1] - e0) / e_ref).tolist(),
+                                 "max_structural_stretch": r[:, 2].tolist()})
+        r = reduce(state["bf16"][1], state["fp32"][1])
+        curve["bf16_vs_fp32"].append({"frame": cp, "rms_width": (np.sqrt(r[:, 0] / nodes) / width).tolist()})
+    return {"scenes": n_scenes, "grid": size, "stride": stride, "seed": seed,
+            "pins": [sc.pin_kind for sc in scenes], "curve": curve}
 
 
 def main():
@@ -76,10 +78,13 @@ def main():
     ap.add_argument("--weights", default=os.path.join(HERE, "weights", "pecnn_ch32.npy"))
     ap.add_argument("--scenes", type=int, default=2)
     ap.add_argument("--size", type=int, default=256)
-    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--stride", type=int, default=10)
+    ap.add_argument("--checkpoints", default="1,2,5,10,20,50,100")
+    ap.add_argument("--seed", type=int, default=5)
     args = ap.parse_args()
     theta = np.load(args.weights, allow_pickle=False)
-    print(json.dumps(evaluate(theta, args.size, args.scenes, args.frames)))
+    cps = [int(x) for x in args.checkpoints.split(",")]
+    print(json.dumps(evaluate(theta, args.size, args.scenes, cps, args.stride, args.seed)))
 
 
 if __name__ == "__main__":

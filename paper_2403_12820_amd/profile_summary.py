@@ -1,0 +1,122 @@
+"""Short text summaries of rocprofv3 output, for the profiles/ folder.
+
+  python -m paper_2403_12820_amd.profile_summary stats KERNEL_STATS.csv OUT.txt --command "..."
+      per-kernel calls, average and total duration (from --kernel-trace --stats)
+
+  python -m paper_2403_12820_amd.profile_summary traffic --kernel NAME --nodes N \
+      --fetch FETCH.csv --write WRITE.csv --copy-fetch CF.csv --copy-write CW.csv \
+      --copy-bytes B OUT.txt --command "..."
+      HBM bytes per launch of one kernel from two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
+      dispatch), each scaled by what the same counter reads for a plain device copy of B bytes.
+
+The traffic summary carries a hash of the kernel's sources; bench.py reports its figure only
+while the sources still hash the same.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = {
+    "cnn_fwd_bf16": ("cnn_fwd_bf16.hip", "cnn_common.hpp", "common.hpp"),
+    "ms_step": ("ms_step.hip", "common.hpp"),
+}
+
+
+def source_hash(kind: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_summary(path: str) -> dict:
+    """key: value lines of a summary file (other lines ignored)."""
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def _stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["rocprofv3 kernel statistics", "command: " + args.command, "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows[: args.top]:
+        lines.append("| %s | %s | %.2f | %.3f | %.1f |" % (
+            r["Name"].split("(")[0][:90], r["Calls"], float(r["AverageNs"]) / 1e3,
+            float(r["TotalDurationNs"]) / 1e6, 100 * float(r["TotalDurationNs"]) / tot))
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(path: str, name: str, counter: str):
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if name in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit("no %s dispatches of %s in %s" % (counter, name, path))
+    return sum(vals) / len(vals), len(vals)
+
+
+def _traffic(args):
+    f_kib, nf = _per_dispatch(args.fetch, args.kernel, "FETCH_SIZE")
+    w_kib, nw = _per_dispatch(args.write, args.kernel, "WRITE_SIZE")
+    # the copy kernel: take its largest dispatch (the 1 GiB copy)
+    cf = max(float(r["Counter_Value"]) for r in csv.DictReader(open(args.copy_fetch)) if r["Counter_Name"] == "FETCH_SIZE")
+    cw = max(float(r["Counter_Value"]) for r in csv.DictReader(open(args.copy_write)) if r["Counter_Name"] == "WRITE_SIZE")
+    kf, kw = args.copy_bytes / (cf * 1024), args.copy_bytes / (cw * 1024)
+    fetch_b, write_b = f_kib * 1024 * kf, w_kib * 1024 * kw
+    lines = [
+        "HBM traffic per launch of %s (rocprofv3 --pmc)" % args.kernel,
+        "command_fetch: " + args.command_fetch,
+        "command_write: " + args.command_write,
+        "command_copy_fetch: " + args.command_copy_fetch,
+        "command_copy_write: " + args.command_copy_write,
+        "kernel: %s" % args.kernel,
+        "nodes: %d" % args.nodes,
+        "dispatches: %d fetch, %d write" % (nf, nw),
+        "fetch_kib_per_dispatch: %.1f" % f_kib,
+        "write_kib_per_dispatch: %.1f" % w_kib,
+        "copy_calibration: a %d-byte device copy reads FETCH_SIZE %.1f KiB and WRITE_SIZE %.1f KiB" % (
+            args.copy_bytes, cf, cw),
+        "fetch_factor: %.4f" % kf,
+        "write_factor: %.4f" % kw,
+        "fetch_bytes: %.0f" % fetch_b,
+        "write_bytes: %.0f" % write_b,
+        "bytes_per_launch: %.0f" % (fetch_b + write_b),
+        "bytes_per_node: %.2f" % ((fetch_b + write_b) / args.nodes),
+        "source_hash: %s" % source_hash(args.kind),
+    ]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    s.add_argument("--top", type=int, default=16)
+    t = sub.add_parser("traffic")
+    t.add_argument("out")
+    t.add_argument("--kind", choices=sorted(KERNEL_SOURCES), required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--nodes", type=int, required=True)
+    for k in ("fetch", "write", "copy-fetch", "copy-write"):
+        t.add_argument("--" + k, required=True)
+        t.add_argument("--command-" + k, required=True)
+    t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    a = ap.parse_args()
+    _stats(a) if a.cmd == "stats" else _traffic(a)
+
+
+if __name__ == "__main__":
+    main()

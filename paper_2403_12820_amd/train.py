@@ -14,6 +14,7 @@ Python only sequences calls; every step runs in the HIP library:
 from __future__ import annotations
 
 import argparse
+import sys
 import json
 import math
 import os
@@ -280,6 +281,7 @@ def main():
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, theta.astype(np.float32), allow_pickle=False)
     rep = args.report or os.path.splitext(args.out)[0] + "_report.json"
+    report = {"command": "python -m paper_2403_12820_amd.train " + " ".join(sys.argv[1:]), **report}
     with open(rep, "w") as f:
         json.dump(report, f, indent=1)
     print(json.dumps({k: v for k, v in report.items() if k != "loss_curve"}))
