@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=("uniform", "batched"), default="uniform",
+                    help="uniform: INSTANCES cloths of SIZE x SIZE; batched: 512 cloths with sides drawn "
+                         "log-uniform in [16, 256] (seed 2)")
     ap.add_argument("--instances", type=int, default=128)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--ch", type=int, default=32)
@@ -109,8 +112,14 @@ def main():
     mat = I.Material()
     stride = 10
     dt_nn = stride * mat.dt
-    sizes = [(args.size, args.size)] * args.instances
-    scenes = I.random_scenes(sizes, seed=5)
+    if args.workload == "uniform":
+        sizes = [(args.size, args.size)] * args.instances
+        scenes = I.random_scenes(sizes, seed=5)
+        workload = "%d cloths of %dx%d" % (args.instances, args.size, args.size)
+    else:
+        sizes = I.loguniform_sizes(512, 16, 256, seed=2)
+        scenes = I.random_scenes(sizes, seed=2)
+        workload = "512 cloths, sides log-uniform in [16, 256] (seed 2)"
     batch = I.make_batch(scenes)
     N = batch.total
     plan = L.Plan.from_batch(batch, dev)
@@ -144,7 +153,8 @@ def main():
     L.pecnn_rollout(plan, model, sim, guard, a, b, args.steps, fb, stats, ws)
     torch.cuda.synchronize()
     t_roll = time.perf_counter() - t0
-    fell = int((fb != 0).sum().item())
+    fb_host = fb.cpu().numpy() != 0
+    fell = int(fb_host.sum())
 
     # ---- the FP32 mass-spring step on the same batch, beside it (stride steps per frame)
     ms_ws = plan.workspace(L.WS_MS_STEP)
@@ -187,7 +197,7 @@ def main():
     alg_bytes = CNN_BYTES_PER_NODE * N
     achieved = alg_bytes / t_kernel / 1e9
 
-    traffic = measured_traffic(N)
+    traffic = measured_traffic(N) if args.workload == "uniform" else None
 
     raw = N * args.steps / t_roll
     value = raw * stride
@@ -197,10 +207,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1e3 * t_roll / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {
-            "workload": "bf16 CNN rollout (Ch=%d) of %d cloths of %dx%d, %d frames of %d simulator steps, guard "
-                        "+ FP64 reductions every %d frames" % (args.ch, args.instances, args.size, args.size,
-                                                               args.steps, stride, args.check_every),
-            "instances": args.instances, "grid": [args.size, args.size], "nodes": N, "channels": args.ch,
+            "workload": "bf16 CNN rollout (Ch=%d) of %s, %d frames of %d simulator steps, guard + FP64 "
+                        "reductions every %d frames" % (args.ch, workload, args.steps, stride, args.check_every),
+            "instances": batch.n, "grid": ([args.size, args.size] if args.workload == "uniform" else
+                                          [int(batch.H.min()), int(batch.H.max())]),
+            "nodes": N, "channels": args.ch,
             "weights": theta_kind, "tiles": {"ms_cfg": ms_cfg, "cnn_cfg": cnn_cfg},
             "frame_dt": dt_nn, "sim_dt": mat.dt, "stride": stride,
             "raw_frames_node_steps_per_s": raw,
@@ -211,7 +222,8 @@ def main():
             "rms_bound": 1e-2, "rms_within_bound": bool(rms.max() <= 1e-2),
             "guard": {"stretch_max": args.stretch_max, "energy_gain_max": args.energy_gain_max,
                       "check_every": args.check_every},
-            "fallback_instances": fell,
+            "fallback_instances": fell, "fallback_rate": fell / batch.n,
+            "fallback_node_fraction": float(sum(int(batch.H[b]) * int(batch.W[b]) for b in np.nonzero(fb_host)[0])) / N,
             "ms_kernel_gbs": MS_BYTES_PER_NODE * N / t_ms_kernel / 1e9,
             "cnn_kernel_ms": t_kernel * 1e3, "ms_kernel_ms": t_ms_kernel * 1e3,
         },
