@@ -50,6 +50,30 @@ __device__ __forceinline__ int find_instance(const int32_t* __restrict__ prefix,
   return lo;
 }
 
+// A persistent workgroup visits its tiles in increasing order, so the owning instance only moves
+// forward: the cursor keeps the current instance's record and tile range, and searches (from
+// the next instance on) only when a tile leaves that range. Most tiles then cost no load at all
+// instead of a chain of dependent loads down a binary search.
+struct TileCursor {
+  int b;          // current instance, -1 before the first tile
+  int start, end; // its tiles: [start, end)
+  InstDev I;
+};
+__device__ __forceinline__ void cursor_init(TileCursor& c) { c.b = -1; c.start = c.end = 0; }
+__device__ __forceinline__ void cursor_seek(TileCursor& c, const InstDev* __restrict__ inst,
+                                            const int32_t* __restrict__ prefix, int n, int t) {
+  if (c.b >= 0 && t < c.end) return;
+  int lo = c.b + 1, hi = n;  // t >= prefix[lo] holds: t >= end = prefix[b + 1] (or lo = 0)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid;
+  }
+  c.b = lo;
+  c.start = prefix[lo];
+  c.end = prefix[lo + 1];
+  c.I = inst[lo];
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give each XCD a
 // contiguous range of tiles so that neighbouring tiles, which share halo rows, hit the same L2.
 // Returns the first tile of this workgroup and the stride between its tiles.

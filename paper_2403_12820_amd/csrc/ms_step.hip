@@ -45,12 +45,14 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
   int first, stride, count;
   xcd_tile_range(n_tiles, first, stride, count);
 
+  TileCursor tcur;
+  cursor_init(tcur);
   auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
     const int t = first + it * stride;
-    const int b = find_instance(prefix, n_inst, t);
-    if (active != nullptr && active[b] == 0) return false;
-    I = inst[b];
-    const int lt = t - prefix[b];
+    cursor_seek(tcur, inst, prefix, n_inst, t);
+    if (active != nullptr && active[tcur.b] == 0) return false;
+    I = tcur.I;
+    const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
     c0 = (lt % tiles_x) * TX;

@@ -1,6 +1,7 @@
-"""Parity at the benchmark's full size, in the launch configuration the benchmark times:
-128 cloths of 256 x 256 (8.4 M nodes), autotuned tiles, checked on sampled instances the
-oracle computes whole; and the 256 x 256 simulator reference over 1000 steps."""
+"""Parity at the full sizes, in the launch configuration the benchmark times (autotuned tiles),
+checked on sampled instances the oracle computes whole: 128 cloths of 256 x 256 (8.4 M nodes);
+the uneven batch of 512 cloths with log-uniform sides; the training-data generation at
+64 x 128 x 128; and the 256 x 256 simulator reference over 1000 steps."""
 import numpy as np
 import pytest
 
@@ -94,3 +95,84 @@ def test_ms_256_thousand_steps_vs_oracle():
     # FP32 rounding of the stiff springs grows over 1000 steps at a few nodes; the RMS stays at
     # the FP32 level
     assert err <= 1e-3 and rms <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def batched_setup():
+    """The uneven batch: 512 cloths with sides log-uniform in [16, 256] (seed 2), autotuned."""
+    import torch
+    from paper_2403_12820_amd import _lib as L
+    batch = I.make_batch(I.random_scenes(I.loguniform_sizes(512, 16, 256, seed=2), seed=2))
+    s1 = batch.state.astype(np.float64)
+    s1[3:] = I.random_array((3, batch.total), seed=61, scale=0.05)
+    s0 = s1.copy()
+    s0[:3] -= 5e-3 * s1[3:]
+    batch.state = s1.astype(np.float32)
+    plan = L.Plan.from_batch(batch)
+    th = (I.init_theta(32, seed=1).astype(np.float64) * 20).astype(np.float32)
+    model = L.make_model(dev_tensor(th), 32, L.PECNN_BF16, dt=5e-3)
+    a, b, c = dev_tensor(s0), dev_tensor(s1), torch.zeros(6, batch.total, device="cuda")
+    L.pecnn_autotune(plan, L.ms_params(MAT), model, a.clone(), b.clone(), c, reps=3)
+    sides = batch.H.astype(int)
+    # smallest, largest, and odd sides (the scalar-load path) between them
+    odd = [int(i) for i in np.nonzero(sides % 2 == 1)[0]]
+    pick = sorted({int(np.argmin(sides)), int(np.argmax(sides)), odd[0], odd[len(odd) // 2], odd[-1]})
+    return L, batch, plan, th, s0.astype(np.float32), s1.astype(np.float32), pick
+
+
+def test_batched_bf16_frame_sampled_instances(batched_setup):
+    import torch
+    L, batch, plan, th, s0, s1, pick = batched_setup
+    model = L.make_model(dev_tensor(th), 32, L.PECNN_BF16, dt=5e-3)
+    out = torch.zeros(6, batch.total, device="cuda")
+    L.pecnn_forward(plan, model, dev_tensor(s0), dev_tensor(s1), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    for b in pick:
+        sl = batch.instance(b)
+        H, W = int(batch.H[b]), int(batch.W[b])
+        a = batch.a_ext[b].astype(np.float64)
+        pin = batch.pin[sl]
+        _, dv_exact = oracle.cnn_forward(H, W, 32, 1.0, 5e-3, a, pin, th.astype(np.float64), s0[:, sl], s1[:, sl])
+        _, dv_emu = oracle.cnn_forward(H, W, 32, 1.0, 5e-3, a, pin, th.astype(np.float64), s0[:, sl], s1[:, sl], emu=7)
+        dv = got[3:, sl] - s1[3:, sl].astype(np.float64) - 5e-3 * a[:, None]
+        for d in (dv, dv_exact, dv_emu):
+            d[:, pin == 1] = 0.0
+        assert rel_inf(dv, dv_exact) <= 1e-2, (b, H)
+        assert rel_inf(dv, dv_emu) <= 2.0 ** -8, (b, H)
+        per_node = np.abs(dv - dv_emu).max(axis=0) / np.abs(dv_emu).max()
+        assert np.median(per_node) <= 1e-5, (b, H)
+
+
+def test_batched_ms_step_sampled_instances(batched_setup):
+    import torch
+    L, batch, plan, th, s0, s1, pick = batched_setup
+    out = torch.zeros(6, batch.total, device="cuda")
+    L.cloth_ms_step(plan, L.ms_params(MAT), dev_tensor(s1), out, 1)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    for b in pick:
+        sl = batch.instance(b)
+        H, W = int(batch.H[b]), int(batch.W[b])
+        width = (W - 1) * float(batch.h[b])
+        ref = oracle.ms_run(H, W, float(batch.h[b]), float(batch.mass[b]), batch.a_ext[b].astype(np.float64),
+                            batch.pin[sl], s1[:, sl], MAT, 1)
+        assert np.abs(got[:3, sl] - ref[:3]).max() <= 1e-5 * width, (b, H)
+        tol_v = max(1e-5 * np.abs(ref[3:]).max(), ms_velocity_floor(batch, MAT))
+        assert np.abs(got[3:, sl] - ref[3:]).max() <= tol_v, (b, H)
+
+
+def test_training_trajectories_full_size():
+    """Data generation at its full size: 64 scenes of 128 x 128 (seed 3), frames every 10 steps;
+    frames 1 and 10 (10 and 100 simulator steps) of sampled scenes against the oracle."""
+    from paper_2403_12820_amd.train import Trajectories
+    scenes = I.random_scenes([(128, 128)] * 64, seed=3)
+    tr = Trajectories(scenes, MAT, 11, 10)
+    width = 127 * float(tr.batch.h[0])
+    for b in (0, 37, 63):
+        sl = tr.batch.instance(b)
+        sc = scenes[b]
+        for f in (1, 10):
+            got = tr.frames[f][:, sl].cpu().numpy().astype(np.float64)
+            ref = oracle.ms_run(128, 128, sc.h, sc.mass, sc.a_ext, sc.pin, sc.state.astype(np.float64), MAT, 10 * f)
+            assert np.abs(got[:3] - ref[:3]).max() <= 1e-5 * width, (b, f)
