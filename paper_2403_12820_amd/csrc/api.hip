@@ -342,6 +342,9 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
   p->ms_cfg = max_hw >= 64 * 64 ? 3 : 2;
   p->cnn_cfg = max_hw >= 64 * 64 ? 0 : 2;
   p->max_hw = max_hw;
+  p->vec4 = (off % 4) == 0;
+  for (int b = 0; b < n; ++b)
+    if (p->W[b] % 4 != 0 || p->off[b] % 4 != 0) p->vec4 = 0;
   p->graph_cache = nullptr;
   *out = p;
   return PECNN_OK;

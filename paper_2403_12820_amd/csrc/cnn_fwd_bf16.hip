@@ -19,7 +19,9 @@ namespace pecnn {
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // WPE: waves per SIMD the register allocation is held to (3 fits the tiles up to 256 nodes).
-template <int CH, int TX, int TY, bool A1, int WPE>
+// VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
+// so the halo rows load as 16-byte pieces; otherwise as single floats.
+template <int CH, int TX, int TY, bool A1, int WPE, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void cnn_fwd_bf16_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_prev, const float* __restrict__ s_cur,
@@ -77,16 +79,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 
   TileCursor tcur;
   cursor_init(tcur);
+  // coordinates of tile number it of this workgroup; false when its instance is skipped
   auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
     const int t = first + it * stride;
     cursor_seek(tcur, inst, prefix, n_inst, t);
-    if (skip != nullptr && skip[tcur.b] != 0) return false;
     I = tcur.I;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
     c0 = (lt % tiles_x) * TX;
-    return true;
+    return skip == nullptr || skip[tcur.b] == 0;
   };
 
   // Per-thread item coordinates do not depend on the tile: float4 item i of this thread is
@@ -101,43 +103,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     it_cq[i] = c * N32 + 4 * q;
   }
 
-  // Issue the halo loads of a tile into registers (they stay in flight during compute).
+  // Issue the halo loads of a tile into registers (they stay in flight during compute). Rows
+  // and columns are clamped to the grid in the addresses; every load has one code path, so
+  // that it writes its final register and nothing waits for it before the tile is staged.
   auto issue = [&](const InstDev& I, int r0, int c0) {
     const int off32 = (int)I.off;
-    const bool vec = ((I.W & 3) == 0) && ((off32 & 3) == 0) && ((N32 & 3) == 0);
-    // the tile and its one-node ring lie inside the grid: no clamping needed (uniform branch)
-    const bool inner = vec && r0 >= 1 && c0 >= 1 && r0 + TY + 1 <= I.H && c0 + TX + 1 <= I.W;
-    if (inner) {
-      const int base = off32 + (r0 - 1) * I.W + c0;
-#pragma unroll
-      for (int i = 0; i < NVT; ++i) {
-        if (NV % 256 == 0 || tid + 256 * i < NV) {
-          const unsigned a = (unsigned)(it_cq[i] + it_rr[i] * I.W + base);
-          pS[i] = gld(reinterpret_cast<const float4*>(s_cur), a);
-          pP[i] = gld(reinterpret_cast<const float4*>(s_prev), a);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < NHT; ++i) {
-        const int j = tid + 256 * i;
-        if (j < NH) {
-          const int row = j >> 1, side = j & 1;
-          const int c = row / HY, rr = row - (row / HY) * HY;
-          const unsigned a = (unsigned)(c * N32 + rr * I.W + base + (side ? TX : -1));
-          hS[i] = gld(s_cur, a);
-          hP[i] = gld(s_prev, a);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int j = tid + 256 * i;
-        if (NP % 256 == 0 || j < NP) {
-          const int ly = j / TX, lx = j - (j / TX) * TX;
-          pp[i] = pin[(unsigned)(base + (ly + 1) * I.W + lx)];
-        }
-      }
-      return;
-    }
 #pragma unroll
     for (int i = 0; i < NVT; ++i) {
       const int j = tid + 256 * i;
@@ -147,9 +117,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         const int gi = min(max(r0 + it_rr[i] - 1, 0), I.H - 1);
         const int col = c0 + 4 * q;
         const unsigned rb = (unsigned)(c * N32 + off32 + gi * I.W);
-        if (vec && col + 3 < I.W) {
-          pS[i] = gld(reinterpret_cast<const float4*>(s_cur), rb + col);
-          pP[i] = gld(reinterpret_cast<const float4*>(s_prev), rb + col);
+        if constexpr (VEC) {
+          // a piece right of the grid loads the last in-grid piece; staging keeps its last column
+          const unsigned a = rb + (unsigned)min(col, I.W - 4);
+          pS[i] = gld(reinterpret_cast<const float4*>(s_cur), a);
+          pP[i] = gld(reinterpret_cast<const float4*>(s_prev), a);
         } else {
           const unsigned j0 = rb + min(col, I.W - 1), j1 = rb + min(col + 1, I.W - 1),
                          j2 = rb + min(col + 2, I.W - 1), j3 = rb + min(col + 3, I.W - 1);
@@ -176,8 +148,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
       const int j = tid + 256 * i;
       if (NP % 256 == 0 || j < NP) {
         const int ly = j / TX, lx = j - (j / TX) * TX;
-        const int gi = r0 + ly, gj = c0 + lx;
-        pp[i] = (gi < I.H && gj < I.W) ? pin[(unsigned)(off32 + gi * I.W + gj)] : (uint8_t)0;
+        const int gi = min(r0 + ly, I.H - 1), gj = min(c0 + lx, I.W - 1);
+        pp[i] = pin[(unsigned)(off32 + gi * I.W + gj)];  // nodes off the grid are never stored
       }
     }
   };
@@ -191,6 +163,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         const int row = j / QV, q = j - (j / QV) * QV;
         const int c = row / HY, rr = row - (row / HY) * HY;
         const int e = rr * RS + 4 + 4 * q;
+
         *reinterpret_cast<float4*>(&tS[c * PLN + e]) = pS[i];
         const float4 d = make_float4(pS[i].x - pP[i].x, pS[i].y - pP[i].y, pS[i].z - pP[i].z, pS[i].w - pP[i].w);
         if (c < 3) {
@@ -227,10 +200,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
   };
 
+  if (count <= 0) return;  // uniform over the workgroup
   InstDev I;
   int r0 = 0, c0 = 0;
-  bool have = count > 0 && decode(0, I, r0, c0);
-  if (have) issue(I, r0, c0);
+  bool have = decode(0, I, r0, c0);
+  issue(I, r0, c0);
 
   for (int it = 0; it < count; ++it) {
     const bool cur = have;
@@ -238,9 +212,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const int rc0 = r0, cc0 = c0;
     if (cur) stage();
     __syncthreads();
-    // prefetch the next tile while this one is computed
-    have = (it + 1 < count) && decode(it + 1, I, r0, c0);
-    if (have) issue(I, r0, c0);
+    if (VEC && cur && cc0 + TX > Ic.W) {
+      // a tile crossing the right edge of the grid: its 16-byte pieces right of the edge hold
+      // the last in-grid piece, but the taps of the last column read the clamped copy of it
+      // one column further; write that column (the only one off the grid that a node reads)
+      const int dst = 4 + (Ic.W - cc0);
+      for (int e = tid; e < 15 * HY; e += 256) {
+        const int pl = e / HY, rr = e - (e / HY) * HY;
+        const int o = rr * RS + dst;
+        if (pl < 6) tS[pl * PLN + o] = tS[pl * PLN + o - 1];
+        else if (pl < 9) tD[(pl - 6) * PLN + o] = tD[(pl - 6) * PLN + o - 1];
+        else tV[(pl - 9) * PLN + o] = tV[(pl - 9) * PLN + o - 1];
+      }
+      __syncthreads();
+    }
+    // prefetch the next tile while this one is computed (after the last tile, a reload of this
+    // one: every iteration issues the same loads, with no branch around them)
+    if (it + 1 < count) have = decode(it + 1, I, r0, c0);
+    issue(I, r0, c0);
 
     if (cur) {
       // per-instance constant part of eq. (5): b_L + dt a_ext
@@ -345,14 +334,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-template <int CH, int TX, int TY, bool A1, int WPE>
+template <int CH, int TX, int TY, bool A1, int WPE, bool VEC>
 static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const float* sc, float* sn,
                         const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
   const int n_tiles = plan->n_tiles[slot];
   static int per_cu = 0;  // resident workgroups per CU of this instantiation
   if (per_cu == 0) {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC>, 256, 0) != hipSuccess ||
         v < 1)
       v = 2;
     per_cu = v;
@@ -361,23 +350,30 @@ static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const
   const int need = ((n_tiles + 7) / 8) * 8;
   if (need < grid) grid = need;
   if (grid < 8) grid = 8;
-  hipLaunchKernelGGL((cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE>), dim3(grid), dim3(256), 0, st, plan->d_inst,
+  hipLaunchKernelGGL((cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC>), dim3(grid), dim3(256), 0, st, plan->d_inst,
                      plan->d_prefix[slot], plan->n, n_tiles, plan->pin, sp, sc, sn, plan->total, theta, dt, alpha,
                      skip);
+}
+
+template <int CH, bool A1, bool VEC>
+static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
+                      const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
+  const int slot = cnn_cfg_slot(cfg);
+  switch (cfg) {
+    case 0: launch_bf16<CH, 64, 4, A1, 3, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 1: launch_bf16<CH, 32, 8, A1, 3, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 2: launch_bf16<CH, 16, 16, A1, 3, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 3: launch_bf16<CH, 64, 8, A1, 2, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    default: return PECNN_E_INVALID;
+  }
+  return PECNN_OK;
 }
 
 template <int CH, bool A1>
 static int bf16_cfg(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                     const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
-  const int slot = cnn_cfg_slot(cfg);
-  switch (cfg) {
-    case 0: launch_bf16<CH, 64, 4, A1, 3>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 1: launch_bf16<CH, 32, 8, A1, 3>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 2: launch_bf16<CH, 16, 16, A1, 3>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 3: launch_bf16<CH, 64, 8, A1, 2>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    default: return PECNN_E_INVALID;
-  }
-  return PECNN_OK;
+  return plan->vec4 ? bf16_cfg_v<CH, A1, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)
+                    : bf16_cfg_v<CH, A1, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
 }
 
 int cnn_forward_bf16_launch(const pecnn_plan* plan, int cfg, const pecnn_model* m, const float* sp,

@@ -132,6 +132,7 @@ struct pecnn_plan {
   int32_t ms_cfg;                       // chosen configs (autotuner or defaults)
   int32_t cnn_cfg;
   int32_t max_hw;                       // largest H*W of an instance
+  int32_t vec4;                         // every row of every plane starts 16-byte aligned
   void* graph_cache;                    // rollout graph cache (host object)
 };
 

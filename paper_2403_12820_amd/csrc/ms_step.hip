@@ -18,7 +18,9 @@ __device__ constexpr Spring kSprings[12] = {
     {1, 1, 1}, {1, -1, 1}, {-1, 1, 1}, {-1, -1, 1},
     {0, 2, 2}, {0, -2, 2}, {2, 0, 2}, {-2, 0, 2}};
 
-template <int TX, int TY, int RY>
+// VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
+// so the tile rows load as 16-byte pieces; otherwise as single floats.
+template <int TX, int TY, int RY, bool VEC>
 __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_in, float* __restrict__ s_out,
@@ -47,21 +49,22 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
 
   TileCursor tcur;
   cursor_init(tcur);
+  // coordinates of tile number it of this workgroup; false when its instance is inactive
   auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
     const int t = first + it * stride;
     cursor_seek(tcur, inst, prefix, n_inst, t);
-    if (active != nullptr && active[tcur.b] == 0) return false;
     I = tcur.I;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
     c0 = (lt % tiles_x) * TX;
-    return true;
+    return active == nullptr || active[tcur.b] != 0;
   };
   // Issue the loads of a tile and its two-node halo (rows and columns clamped to the grid; the
-  // clamped copies are never used as springs, whose ends are checked against the grid).
+  // clamped copies are never used as springs, whose ends are checked against the grid). Every
+  // load has one code path, so that it writes its final register and nothing waits for it
+  // before the tile is staged.
   auto issue = [&](const InstDev& I, int r0, int c0) {
-    const bool vec = ((I.W & 3) == 0) && ((I.off & 3) == 0) && ((N & 3) == 0);
 #pragma unroll
     for (int i = 0; i < NVT; ++i) {
       const int j = tid + NT * i;
@@ -71,8 +74,9 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
         const int gi = min(max(r0 + rr - 2, 0), I.H - 1);
         const int col = c0 + 4 * q;
         const unsigned rb = (unsigned)(c * (int)N + (int)I.off + gi * I.W);
-        if (vec && col + 3 < I.W) {
-          pv[i] = gld(reinterpret_cast<const float4*>(s_in), rb + col);
+        if constexpr (VEC) {
+          // a piece right of the grid loads the last in-grid piece (never a spring end)
+          pv[i] = gld(reinterpret_cast<const float4*>(s_in), rb + (unsigned)min(col, I.W - 4));
         } else {
           pv[i] = make_float4(gld(s_in, rb + min(col, I.W - 1)), gld(s_in, rb + min(col + 1, I.W - 1)),
                               gld(s_in, rb + min(col + 2, I.W - 1)), gld(s_in, rb + min(col + 3, I.W - 1)));
@@ -95,8 +99,8 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
       const int j = tid + NT * i;
       if (NP % NT == 0 || j < NP) {
         const int ly = j / TX, lx = j - (j / TX) * TX;
-        const int gi = r0 + ly, gj = c0 + lx;
-        pp[i] = (gi < I.H && gj < I.W) ? pin[(unsigned)((int)I.off + gi * I.W + gj)] : (uint8_t)0;
+        const int gi = min(r0 + ly, I.H - 1), gj = min(c0 + lx, I.W - 1);
+        pp[i] = pin[(unsigned)((int)I.off + gi * I.W + gj)];  // nodes off the grid are never stored
       }
     }
   };
@@ -126,18 +130,20 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     }
   };
 
+  if (count <= 0) return;  // uniform over the workgroup
   InstDev I;
   int r0 = 0, c0 = 0;
-  bool have = count > 0 && decode(0, I, r0, c0);
-  if (have) issue(I, r0, c0);
+  bool have = decode(0, I, r0, c0);
+  issue(I, r0, c0);
   for (int it = 0; it < count; ++it) {
     const bool cur = have;
     const InstDev Ic = I;
     const int rc0 = r0, cc0 = c0;
     if (cur) stage();
     __syncthreads();
-    have = (it + 1 < count) && decode(it + 1, I, r0, c0);
-    if (have) issue(I, r0, c0);
+    // prefetch the next tile (after the last tile, a reload of this one: no branch around it)
+    if (it + 1 < count) have = decode(it + 1, I, r0, c0);
+    issue(I, r0, c0);
 
     if (cur) {
       const float L[3] = {Ic.h, Ic.h * 1.41421356237309515f, 2.f * Ic.h};
@@ -211,9 +217,14 @@ static void launch_ms(const pecnn_plan* plan, int slot, const MsParamsDev& P, co
                       float* out, const uint8_t* active, hipStream_t st) {
   const int n_tiles = plan->n_tiles[slot];
   const int grid = grid_for(n_tiles, 8);
-  hipLaunchKernelGGL((ms_step_kernel<TX, TY, RY>), dim3(grid), dim3(TX * (TY / RY)), 0, st,
-                     plan->d_inst, plan->d_prefix[slot], plan->n, n_tiles, plan->pin, in, out,
-                     plan->total, P, active);
+  if (plan->vec4)
+    hipLaunchKernelGGL((ms_step_kernel<TX, TY, RY, true>), dim3(grid), dim3(TX * (TY / RY)), 0, st,
+                       plan->d_inst, plan->d_prefix[slot], plan->n, n_tiles, plan->pin, in, out,
+                       plan->total, P, active);
+  else
+    hipLaunchKernelGGL((ms_step_kernel<TX, TY, RY, false>), dim3(grid), dim3(TX * (TY / RY)), 0, st,
+                       plan->d_inst, plan->d_prefix[slot], plan->n, n_tiles, plan->pin, in, out,
+                       plan->total, P, active);
 }
 
 MsParamsDev ms_params_dev(const cloth_ms_params* p) {

@@ -20,6 +20,15 @@ def ragged_sizes():
     return [(1, 2), (2, 2), (17, 23), (2, 257), (33, 65), (5, 3), (64, 64), (3, 70)]
 
 
+def aligned_sizes():
+    """Every width a multiple of 4 (16-byte row pieces), with tiles crossing the right and bottom
+    grid edges: tiny, one-row, tall, and several tiles with ragged tails."""
+    return [(4, 4), (9, 20), (33, 68), (2, 132), (17, 36), (64, 64), (3, 100), (40, 12)]
+
+
+SIZE_SETS = {"ragged": ragged_sizes, "aligned": aligned_sizes}
+
+
 def perturbed_batch(sizes, seed, vel=0.05, pos=0.15, mat=None):
     """Random scenes with deformed positions and random velocities (float32 state)."""
     scenes = I.random_scenes(sizes, seed, noise_sigma=1e-3, mat=mat)

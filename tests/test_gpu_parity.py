@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 from paper_2403_12820_amd import inputs as I
-from tests.gpu_util import dev_tensor, perturbed_batch, ragged_sizes, ms_velocity_floor, rel_inf
+from tests.gpu_util import SIZE_SETS, dev_tensor, perturbed_batch, ragged_sizes, ms_velocity_floor, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -49,9 +49,10 @@ def _ms_gpu(L, torch, batch, s, n_steps=1, cfg=None, mat=MAT, active=None):
 
 
 # ------------------------------------------------------------------ mass-spring step
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
-def test_ms_step_matches_oracle(torch_mod, L, cfg):
-    sizes = ragged_sizes() + [(32, 32)]
+def test_ms_step_matches_oracle(torch_mod, L, cfg, sizes_kind):
+    sizes = SIZE_SETS[sizes_kind]() + [(32, 32)]
     batch = perturbed_batch(sizes, seed=100)
     got = _ms_gpu(L, torch_mod, batch, batch.state, 1, cfg)
     ref = oracle.batch_ms_step(batch, batch.state, MAT, 1)
@@ -61,8 +62,9 @@ def test_ms_step_matches_oracle(torch_mod, L, cfg):
     assert np.abs(got[3:] - ref[3:]).max() <= tol_v, (np.abs(got[3:] - ref[3:]).max(), tol_v)
 
 
-def test_ms_tile_configs_bitwise_equal(torch_mod, L):
-    batch = perturbed_batch(ragged_sizes(), seed=101)
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
+def test_ms_tile_configs_bitwise_equal(torch_mod, L, sizes_kind):
+    batch = perturbed_batch(SIZE_SETS[sizes_kind](), seed=101)
     outs = [_ms_gpu(L, torch_mod, batch, batch.state, 3, cfg) for cfg in range(5)]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
@@ -173,9 +175,10 @@ def test_cnn_forward_fp32_matches_oracle(torch_mod, L, ch, cfg):
     assert rel_inf(dv, dv_ref) <= 1e-5, rel_inf(dv, dv_ref)
 
 
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
 @pytest.mark.parametrize("ch", [16, 32])
-def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch):
-    batch, s0, s1, th = _cnn_inputs(ragged_sizes(), 300 + ch, ch, 30.0)
+def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch, sizes_kind):
+    batch, s0, s1, th = _cnn_inputs(SIZE_SETS[sizes_kind](), 300 + ch, ch, 30.0)
     got = _cnn_gpu(L, torch_mod, batch, s0, s1, th, ch, L.PECNN_BF16)
     _, dv_exact = oracle.batch_cnn_forward(batch, ch, 1.0, 5e-3, th.astype(np.float64), s0, s1)
     _, dv_emu = oracle.batch_cnn_forward(batch, ch, 1.0, 5e-3, th.astype(np.float64), s0, s1, emu=7)
@@ -196,9 +199,10 @@ def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch):
     assert np.quantile(per_node, 0.99) <= 2e-4, np.quantile(per_node, 0.99)
 
 
-def test_cnn_tile_configs_bitwise_equal(torch_mod, L):
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
+def test_cnn_tile_configs_bitwise_equal(torch_mod, L, sizes_kind):
     for prec in (0, 1):
-        batch, s0, s1, th = _cnn_inputs(ragged_sizes(), 400, 32, 10.0)
+        batch, s0, s1, th = _cnn_inputs(SIZE_SETS[sizes_kind](), 400, 32, 10.0)
         outs = [_cnn_gpu(L, torch_mod, batch, s0, s1, th, 32, prec, cfg=c) for c in range(4)]
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
