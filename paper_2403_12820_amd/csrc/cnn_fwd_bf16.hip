@@ -210,7 +210,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const bool cur = have;
     const InstDev Ic = I;
     const int rc0 = r0, cc0 = c0;
-    if (cur) stage();
+    // staged also for a skipped tile: then every prefetched register has been consumed on
+    // every path when the next loads reuse it, and no load waits on older stores
+    stage();
     __syncthreads();
     if (VEC && cur && cc0 + TX > Ic.W) {
       // a tile crossing the right edge of the grid: its 16-byte pieces right of the edge hold

@@ -139,7 +139,9 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const bool cur = have;
     const InstDev Ic = I;
     const int rc0 = r0, cc0 = c0;
-    if (cur) stage();
+    // staged also for a skipped tile: then every prefetched register has been consumed on
+    // every path when the next loads reuse it, and no load waits on older stores
+    stage();
     __syncthreads();
     // prefetch the next tile (after the last tile, a reload of this one: no branch around it)
     if (it + 1 < count) have = decode(it + 1, I, r0, c0);

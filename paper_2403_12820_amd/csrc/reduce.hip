@@ -10,26 +10,26 @@ namespace pecnn {
 struct HalfSpring { int dy, dx, fam; };
 __device__ constexpr HalfSpring kHalf[6] = {{0, 1, 0}, {1, 0, 0}, {1, 1, 1}, {1, -1, 1}, {0, 2, 2}, {2, 0, 2}};
 
+// Block reductions of 256 threads in a fixed order: an xor tree inside each 64-lane wave
+// (cross-lane moves, no barrier), then the four wave results in wave order through LDS.
+constexpr int kWaves = 256 / 64;
+
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* sh) {
-  sh[threadIdx.x] = v;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
-    __syncthreads();
-  }
   T r = sh[0];
-  __syncthreads();
+  for (int k = 1; k < kWaves; ++k) r += sh[k];
+  __syncthreads();  // sh is reused by the next reduction
   return r;
 }
 __device__ __forceinline__ double block_max(double v, double* sh) {
-  sh[threadIdx.x] = v;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-    __syncthreads();
-  }
   double r = sh[0];
+  for (int k = 1; k < kWaves; ++k) r = fmax(r, sh[k]);
   __syncthreads();
   return r;
 }
