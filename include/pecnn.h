@@ -57,7 +57,7 @@ typedef struct {
 
 typedef struct pecnn_plan pecnn_plan; /* opaque host handle */
 
-/* Device bytes needed by a plan for this batch (instance records and tile tables). */
+/* Device bytes needed by a plan for this batch (instance records, tile tables, node-chunk table). */
 int pecnn_plan_device_bytes(const pecnn_batch_desc* desc, size_t* bytes);
 
 /* Build a plan: validates the batch, writes its tables into dev_mem (device, caller-owned,

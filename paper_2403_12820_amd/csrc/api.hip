@@ -252,7 +252,10 @@ int pecnn_plan_device_bytes(const pecnn_batch_desc* d, size_t* bytes) {
   int rc = check_desc(d);
   if (rc) return rc;
   if (!bytes) { set_error("null bytes"); return PECNN_E_INVALID; }
-  *bytes = align256((size_t)d->n * sizeof(InstDev)) + kNumCfg * align256((size_t)(d->n + 1) * sizeof(int32_t));
+  std::vector<int64_t> nt;
+  tile_counts(d, nt);
+  *bytes = align256((size_t)d->n * sizeof(InstDev)) + kNumCfg * align256((size_t)(d->n + 1) * sizeof(int32_t)) +
+           align256((size_t)nt[kCfgChunk] * sizeof(int32_t));
   return PECNN_OK;
 }
 
@@ -304,6 +307,16 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
     pre[n] = acc;
     o += align256((size_t)(n + 1) * sizeof(int32_t));
   }
+  // instance of every node chunk (the node-parallel kernels look it up instead of searching)
+  const size_t chunk_off = o;
+  {
+    int32_t* ci = (int32_t*)(host.data() + o);
+    int64_t t = 0;
+    for (int b = 0; b < n; ++b) {
+      const int64_t chunks = ((int64_t)d->H[b] * d->W[b] + kChunk - 1) / kChunk;
+      for (int64_t k = 0; k < chunks; ++k) ci[t++] = b;
+    }
+  }
   hipStream_t st = (hipStream_t)stream;
   PECNN_HIP(hipMemcpyAsync(dev_mem, host.data(), need, hipMemcpyHostToDevice, st));
   PECNN_HIP(hipStreamSynchronize(st));
@@ -338,6 +351,7 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
     p->d_prefix[c] = (int32_t*)((char*)dev_mem + pre_off[c]);
     p->n_tiles[c] = (int32_t)nt[c];
   }
+  p->d_chunk_inst = (int32_t*)((char*)dev_mem + chunk_off);
   // defaults: wide rows for large instances, square tiles when most instances are small
   p->ms_cfg = max_hw >= 64 * 64 ? 3 : 2;
   p->cnn_cfg = max_hw >= 64 * 64 ? 0 : 2;

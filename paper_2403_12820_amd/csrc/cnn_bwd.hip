@@ -48,18 +48,20 @@ __host__ __device__ inline int64_t fac_floats(int64_t n, int rows) { return (n +
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Node kernels walk the batch in chunks of kChunk nodes (tile prefix of the chunk config).
-__device__ __forceinline__ bool chunk_node(const InstDev* inst, const int32_t* prefix, int n_inst, int t,
-                                           int& b, int64_t& local) {
-  b = find_instance(prefix, n_inst, t);
-  local = (int64_t)(t - prefix[b]) * kChunk + threadIdx.x;
-  const int64_t n = (int64_t)inst[b].H * inst[b].W;
-  return local < n;
+// Node kernels walk the batch in chunks of kChunk nodes; chunk t belongs to instance
+// chunk_inst[t] and starts at its node (t - prefix[b]) kChunk.
+// Node indices inside an instance fit 32 bits (the batch size limit), so the row / column split
+// is a 32-bit division.
+__device__ __forceinline__ bool chunk_node(const InstDev* inst, const int32_t* prefix, const int32_t* chunk_inst,
+                                           int t, int& b, int& local) {
+  b = chunk_inst[t];
+  local = (t - prefix[b]) * kChunk + (int)threadIdx.x;
+  return local < inst[b].H * inst[b].W;
 }
 
 template <int CH>
 __global__ __launch_bounds__(256) void bwd_node_kernel(
-    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst,
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_prev, const float* __restrict__ s_cur,
     const float* __restrict__ g_next, int64_t N, const float* __restrict__ theta, float dt, float alpha,
     float* __restrict__ fac) {
@@ -72,10 +74,10 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
   __syncthreads();
 
   int b;
-  int64_t local;
-  if (!chunk_node(inst, prefix, n_inst, blockIdx.x, b, local)) return;
+  int local;
+  if (!chunk_node(inst, prefix, chunk_inst, blockIdx.x, b, local)) return;
   const InstDev I = inst[b];
-  const int i = (int)(local / I.W), j = (int)(local % I.W);
+  const int i = local / I.W, j = local - (local / I.W) * I.W;
   const int64_t p = I.off + local;
   const BwdLayout L = bwd_layout(CH);
   float* __restrict__ F = fac + fac_node(p, L.rows);  // feature row r of node p lives at F[r * 32]
@@ -183,14 +185,14 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
 // For node q: g_cur/g_prev += direct terms of eq. (5) + adjoint of the clamped, centre-differenced
 // im2col: a tap (c, o) of node p read S_c(clamp(p + o)) (and, for positions, -S_c(p)).
 __global__ __launch_bounds__(256) void bwd_gather_kernel(
-    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst,
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
     const uint8_t* __restrict__ pin, const float* __restrict__ g_next, int64_t N, float dt, int ch,
     const float* __restrict__ fac, float* __restrict__ g_cur, float* __restrict__ g_prev) {
   int b;
-  int64_t local;
-  if (!chunk_node(inst, prefix, n_inst, blockIdx.x, b, local)) return;
+  int local;
+  if (!chunk_node(inst, prefix, chunk_inst, blockIdx.x, b, local)) return;
   const InstDev I = inst[b];
-  const int qi = (int)(local / I.W), qj = (int)(local % I.W);
+  const int qi = local / I.W, qj = local - (local / I.W) * I.W;
   const int64_t q = I.off + local;
   const BwdLayout L = bwd_layout(ch);
   const float* __restrict__ gus = fac + L.gus * 32;
@@ -439,15 +441,15 @@ int backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* s
   const int32_t* pre = plan->d_prefix[kCfgChunk];
   const int P = (int)theta_count(m->ch);
   if (m->ch == 16) {
-    hipLaunchKernelGGL(bwd_node_kernel<16>, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->n, plan->pin, sp, sc,
+    hipLaunchKernelGGL(bwd_node_kernel<16>, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, sp, sc,
                        gn, plan->total, m->theta, m->dt, m->isru_alpha, fac);
   } else {
-    hipLaunchKernelGGL(bwd_node_kernel<32>, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->n, plan->pin, sp, sc,
+    hipLaunchKernelGGL(bwd_node_kernel<32>, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, sp, sc,
                        gn, plan->total, m->theta, m->dt, m->isru_alpha, fac);
   }
   PECNN_LAUNCH_CHECK("bwd_node_kernel");
   if (gc || gp) {
-    hipLaunchKernelGGL(bwd_gather_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->n, plan->pin, gn,
+    hipLaunchKernelGGL(bwd_gather_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, gn,
                        plan->total, m->dt, m->ch, fac, gc, gp);
     PECNN_LAUNCH_CHECK("bwd_gather_kernel");
   }

@@ -82,13 +82,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   // coordinates of tile number it of this workgroup; false when its instance is skipped
   auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
     const int t = first + it * stride;
-    cursor_seek(tcur, inst, prefix, n_inst, t);
+    cursor_seek(tcur, inst, prefix, n_inst, t, skip);
     I = tcur.I;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
     c0 = (lt % tiles_x) * TX;
-    return skip == nullptr || skip[tcur.b] == 0;
+    return tcur.flag == 0;
   };
 
   // Per-thread item coordinates do not depend on the tile: float4 item i of this thread is

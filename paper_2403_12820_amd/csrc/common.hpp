@@ -57,11 +57,14 @@ __device__ __forceinline__ int find_instance(const int32_t* __restrict__ prefix,
 struct TileCursor {
   int b;          // current instance, -1 before the first tile
   int start, end; // its tiles: [start, end)
+  int flag;       // flags[b] when a per-instance flag array is given, else 0
   InstDev I;
 };
 __device__ __forceinline__ void cursor_init(TileCursor& c) { c.b = -1; c.start = c.end = 0; }
+template <typename F>
 __device__ __forceinline__ void cursor_seek(TileCursor& c, const InstDev* __restrict__ inst,
-                                            const int32_t* __restrict__ prefix, int n, int t) {
+                                            const int32_t* __restrict__ prefix, int n, int t,
+                                            const F* __restrict__ flags) {
   if (c.b >= 0 && t < c.end) return;
   int lo = c.b + 1, hi = n;  // t >= prefix[lo] holds: t >= end = prefix[b + 1] (or lo = 0)
   while (hi - lo > 1) {
@@ -72,6 +75,7 @@ __device__ __forceinline__ void cursor_seek(TileCursor& c, const InstDev* __rest
   c.start = prefix[lo];
   c.end = prefix[lo + 1];
   c.I = inst[lo];
+  c.flag = flags ? (int)flags[lo] : 0;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give each XCD a
@@ -128,6 +132,7 @@ struct pecnn_plan {
   const uint8_t* pin;                   // device, caller-owned
   pecnn::InstDev* d_inst;               // device, inside the caller's plan memory
   int32_t* d_prefix[pecnn::kNumCfg];    // device prefix of tiles per instance, per config
+  int32_t* d_chunk_inst;                // device: instance of every node chunk (kChunk nodes)
   int32_t n_tiles[pecnn::kNumCfg];
   int32_t ms_cfg;                       // chosen configs (autotuner or defaults)
   int32_t cnn_cfg;

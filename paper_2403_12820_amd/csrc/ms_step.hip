@@ -52,13 +52,13 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
   // coordinates of tile number it of this workgroup; false when its instance is inactive
   auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
     const int t = first + it * stride;
-    cursor_seek(tcur, inst, prefix, n_inst, t);
+    cursor_seek(tcur, inst, prefix, n_inst, t, active);
     I = tcur.I;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
     c0 = (lt % tiles_x) * TX;
-    return active == nullptr || active[tcur.b] != 0;
+    return active == nullptr || tcur.flag != 0;
   };
   // Issue the loads of a tile and its two-node halo (rows and columns clamped to the grid; the
   // clamped copies are never used as springs, whose ends are checked against the grid). Every

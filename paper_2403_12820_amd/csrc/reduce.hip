@@ -35,16 +35,17 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 }
 
 __global__ __launch_bounds__(256) void reduce_chunk_kernel(
-    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int64_t N,
-    const float* __restrict__ s, const float* __restrict__ s_ref, MsParamsDev P, double* __restrict__ partial) {
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+    int64_t N, const float* __restrict__ s, const float* __restrict__ s_ref, MsParamsDev P,
+    double* __restrict__ partial) {
   __shared__ double sh[256];
   const int t = blockIdx.x;
-  const int b = find_instance(prefix, n_inst, t);
+  const int b = chunk_inst[t];
   const InstDev I = inst[b];
-  const int64_t local = (int64_t)(t - prefix[b]) * kChunk + threadIdx.x;
+  const int local = (t - prefix[b]) * kChunk + (int)threadIdx.x;  // 32-bit: within one instance
   double e2 = 0.0, en = 0.0, st_s = 0.0, st_a = 0.0;
-  if (local < (int64_t)I.H * I.W) {
-    const int i = (int)(local / I.W), j = (int)(local % I.W);
+  if (local < I.H * I.W) {
+    const int i = local / I.W, j = local - (local / I.W) * I.W;
     const int64_t p = I.off + local;
     const double m = I.mass;
     const double ge[3] = {(double)P.g[0] + I.ax, (double)P.g[1] + I.ay, (double)P.g[2] + I.az};
@@ -91,21 +92,29 @@ __global__ __launch_bounds__(256) void reduce_chunk_kernel(
   }
 }
 
-__global__ void reduce_final_kernel(const int32_t* __restrict__ prefix, int n_inst, const double* __restrict__ partial,
-                                    double* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_inst) return;
+// One block per instance: thread k takes chunks k, k + 256, ... of the instance in order, then
+// a fixed-order block reduction.
+__global__ __launch_bounds__(256) void reduce_final_kernel(const int32_t* __restrict__ prefix, int n_inst,
+                                                           const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double sh[kWaves];
+  const int b = blockIdx.x;
   double e2 = 0.0, en = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int t = prefix[b]; t < prefix[b + 1]; ++t) {
+  for (int t = prefix[b] + (int)threadIdx.x; t < prefix[b + 1]; t += 256) {
     e2 += partial[4 * t + 0];
     en += partial[4 * t + 1];
     s1 = fmax(s1, partial[4 * t + 2]);
     s2 = fmax(s2, partial[4 * t + 3]);
   }
-  out[4 * b + 0] = e2;
-  out[4 * b + 1] = en;
-  out[4 * b + 2] = s1;
-  out[4 * b + 3] = s2;
+  e2 = block_sum(e2, sh);
+  en = block_sum(en, sh);
+  s1 = block_max(s1, sh);
+  s2 = block_max(s2, sh);
+  if (threadIdx.x == 0) {
+    out[4 * b + 0] = e2;
+    out[4 * b + 1] = en;
+    out[4 * b + 2] = s1;
+    out[4 * b + 3] = s2;
+  }
 }
 
 size_t reduce_ws_bytes(const pecnn_plan* plan) {
@@ -117,9 +126,9 @@ int reduce_launch(const pecnn_plan* plan, const MsParamsDev& P, const float* s, 
   const int nt = plan->n_tiles[kCfgChunk];
   double* partial = (double*)ws;
   hipLaunchKernelGGL(reduce_chunk_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk],
-                     plan->n, plan->total, s, s_ref, P, partial);
+                     plan->d_chunk_inst, plan->total, s, s_ref, P, partial);
   PECNN_LAUNCH_CHECK("reduce_chunk_kernel");
-  hipLaunchKernelGGL(reduce_final_kernel, dim3((plan->n + 255) / 256), dim3(256), 0, st, plan->d_prefix[kCfgChunk],
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(plan->n), dim3(256), 0, st, plan->d_prefix[kCfgChunk],
                      plan->n, partial, out);
   PECNN_LAUNCH_CHECK("reduce_final_kernel");
   return PECNN_OK;
@@ -127,16 +136,16 @@ int reduce_launch(const pecnn_plan* plan, const MsParamsDev& P, const float* s, 
 
 // ---------------------------------------------------------------- loss (eq. 8, data term)
 __global__ __launch_bounds__(256) void loss_chunk_kernel(
-    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int64_t N,
-    const uint8_t* __restrict__ pin, const float* __restrict__ sh_, const float* __restrict__ st_, float isx2,
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+    int64_t N, const uint8_t* __restrict__ pin, const float* __restrict__ sh_, const float* __restrict__ st_, float isx2,
     float isv2, float gscale, double* __restrict__ partial, float* __restrict__ g) {
   __shared__ double sh[256];
   const int t = blockIdx.x;
-  const int b = find_instance(prefix, n_inst, t);
+  const int b = chunk_inst[t];
   const InstDev I = inst[b];
-  const int64_t local = (int64_t)(t - prefix[b]) * kChunk + threadIdx.x;
+  const int local = (t - prefix[b]) * kChunk + (int)threadIdx.x;
   double acc = 0.0;
-  if (local < (int64_t)I.H * I.W) {
+  if (local < I.H * I.W) {
     const int64_t p = I.off + local;
     if (!pin[p]) {
       for (int c = 0; c < 6; ++c) {
@@ -166,8 +175,8 @@ int loss_launch(const pecnn_plan* plan, const float* s_hat, const float* s_true,
   double* partial = (double*)ws;
   const float isx2 = 1.f / (sx * sx), isv2 = 1.f / (sv * sv);
   const float gscale = (float)(2.0 * (double)w / (double)n_free);
-  hipLaunchKernelGGL(loss_chunk_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk], plan->n,
-                     plan->total, plan->pin, s_hat, s_true, isx2, isv2, gscale, partial, g);
+  hipLaunchKernelGGL(loss_chunk_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk],
+                     plan->d_chunk_inst, plan->total, plan->pin, s_hat, s_true, isx2, isv2, gscale, partial, g);
   PECNN_LAUNCH_CHECK("loss_chunk_kernel");
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, partial, nt, (double)w / (double)n_free, loss);
   PECNN_LAUNCH_CHECK("loss_final_kernel");
