@@ -80,15 +80,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   TileCursor tcur;
   cursor_init(tcur);
   // coordinates of tile number it of this workgroup; false when its instance is skipped
-  auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
-    const int t = first + it * stride;
-    cursor_seek(tcur, inst, prefix, n_inst, t, skip);
+  // This workgroup's tiles are first, first + stride, ... below t_end. Tiles of skipped
+  // instances are passed over whole: the cursor jumps to the first tile of the sequence beyond
+  // the instance, so they cost no loads, staging or compute.
+  const int t_end = first + count * stride;
+  auto next_tile = [&](int t) -> int {
+    while (t < t_end) {
+      cursor_seek(tcur, inst, prefix, n_inst, t, skip);
+      if (tcur.flag == 0) return t;
+      t = first + ((tcur.end - first + stride - 1) / stride) * stride;
+    }
+    return -1;
+  };
+  // coordinates of tile t, whose instance the cursor holds
+  auto coords = [&](int t, InstDev& I, int& r0, int& c0) {
     I = tcur.I;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
     c0 = (lt % tiles_x) * TX;
-    return tcur.flag == 0;
   };
 
   // Per-thread item coordinates do not depend on the tile: float4 item i of this thread is
@@ -200,21 +210,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
   };
 
-  if (count <= 0) return;  // uniform over the workgroup
+  int t = next_tile(first);
+  if (t < 0) return;  // uniform over the workgroup
   InstDev I;
   int r0 = 0, c0 = 0;
-  bool have = decode(0, I, r0, c0);
+  coords(t, I, r0, c0);
   issue(I, r0, c0);
 
-  for (int it = 0; it < count; ++it) {
-    const bool cur = have;
+  for (;;) {
     const InstDev Ic = I;
     const int rc0 = r0, cc0 = c0;
-    // staged also for a skipped tile: then every prefetched register has been consumed on
-    // every path when the next loads reuse it, and no load waits on older stores
+    // every prefetched register is consumed here on every path, so the next loads that reuse
+    // them never wait on older stores
     stage();
     __syncthreads();
-    if (VEC && cur && cc0 + TX > Ic.W) {
+    if (VEC && cc0 + TX > Ic.W) {
       // a tile crossing the right edge of the grid: its 16-byte pieces right of the edge hold
       // the last in-grid piece, but the taps of the last column read the clamped copy of it
       // one column further; write that column (the only one off the grid that a node reads)
@@ -230,10 +240,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
     // prefetch the next tile while this one is computed (after the last tile, a reload of this
     // one: every iteration issues the same loads, with no branch around them)
-    if (it + 1 < count) have = decode(it + 1, I, r0, c0);
+    const int tn = next_tile(t + stride);
+    if (tn >= 0) coords(tn, I, r0, c0);
     issue(I, r0, c0);
 
-    if (cur) {
+    {
       // per-instance constant part of eq. (5): b_L + dt a_ext
       const float cx = __builtin_fmaf(dt, Ic.ax, bias0), cy = __builtin_fmaf(dt, Ic.ay, bias1),
                   cz = __builtin_fmaf(dt, Ic.az, bias2);
@@ -333,6 +344,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
       }
     }
     __syncthreads();
+    if (tn < 0) break;  // uniform
+    t = tn;
   }
 }
 

@@ -50,15 +50,25 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
   TileCursor tcur;
   cursor_init(tcur);
   // coordinates of tile number it of this workgroup; false when its instance is inactive
-  auto decode = [&](int it, InstDev& I, int& r0, int& c0) -> bool {
-    const int t = first + it * stride;
-    cursor_seek(tcur, inst, prefix, n_inst, t, active);
+  // This workgroup's tiles are first, first + stride, ... below t_end. Tiles of skipped
+  // instances are passed over whole: the cursor jumps to the first tile of the sequence beyond
+  // the instance, so they cost no loads, staging or compute.
+  const int t_end = first + count * stride;
+  auto next_tile = [&](int t) -> int {
+    while (t < t_end) {
+      cursor_seek(tcur, inst, prefix, n_inst, t, active);
+      if ((active == nullptr || tcur.flag != 0)) return t;
+      t = first + ((tcur.end - first + stride - 1) / stride) * stride;
+    }
+    return -1;
+  };
+  // coordinates of tile t, whose instance the cursor holds
+  auto coords = [&](int t, InstDev& I, int& r0, int& c0) {
     I = tcur.I;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
     c0 = (lt % tiles_x) * TX;
-    return active == nullptr || tcur.flag != 0;
   };
   // Issue the loads of a tile and its two-node halo (rows and columns clamped to the grid; the
   // clamped copies are never used as springs, whose ends are checked against the grid). Every
@@ -130,24 +140,26 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     }
   };
 
-  if (count <= 0) return;  // uniform over the workgroup
+  int t = next_tile(first);
+  if (t < 0) return;  // uniform over the workgroup
   InstDev I;
   int r0 = 0, c0 = 0;
-  bool have = decode(0, I, r0, c0);
+  coords(t, I, r0, c0);
   issue(I, r0, c0);
-  for (int it = 0; it < count; ++it) {
-    const bool cur = have;
+
+  for (;;) {
     const InstDev Ic = I;
     const int rc0 = r0, cc0 = c0;
-    // staged also for a skipped tile: then every prefetched register has been consumed on
-    // every path when the next loads reuse it, and no load waits on older stores
+    // every prefetched register is consumed here on every path, so the next loads that reuse
+    // them never wait on older stores
     stage();
     __syncthreads();
     // prefetch the next tile (after the last tile, a reload of this one: no branch around it)
-    if (it + 1 < count) have = decode(it + 1, I, r0, c0);
+    const int tn = next_tile(t + stride);
+    if (tn >= 0) coords(tn, I, r0, c0);
     issue(I, r0, c0);
 
-    if (cur) {
+    {
       const float L[3] = {Ic.h, Ic.h * 1.41421356237309515f, 2.f * Ic.h};
       const float tiny = 1e-24f * Ic.h * Ic.h;
       const float sc = P.dt / Ic.mass;
@@ -203,6 +215,8 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
       }
     }
     __syncthreads();
+    if (tn < 0) break;  // uniform
+    t = tn;
   }
 }
 
