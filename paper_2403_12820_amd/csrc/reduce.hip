@@ -61,6 +61,8 @@ __global__ __launch_bounds__(256) void reduce_chunk_kernel(
     }
     const double h = I.h;
     const double L[3] = {h, 1.4142135623730951 * h, 2.0 * h};
+    const double ih = 1.0 / h;  // one division per node; the stretch ratios multiply
+    const double iL[3] = {ih, 0.70710678118654752 * ih, 0.5 * ih};
     for (int q = 0; q < 6; ++q) {
       const int ii = i + kHalf[q].dy, jj = j + kHalf[q].dx;
       // structural springs pointing backwards are visited by the other end; stretch needs all
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(256) void reduce_chunk_kernel(
       const int f = kHalf[q].fam;
       const double dr = r - L[f];
       en += 0.5 * (double)P.k[f] * dr * dr;
-      const double ratio = r / L[f];
+      const double ratio = r * iL[f];
       if (f == 0) st_s = fmax(st_s, ratio);
       st_a = fmax(st_a, ratio);
     }
