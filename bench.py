@@ -83,7 +83,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", choices=("uniform", "batched"), default="uniform",
                     help="uniform: INSTANCES cloths of SIZE x SIZE; batched: 512 cloths with sides drawn "
                          "log-uniform in [16, 256] (seed 2)")
