@@ -54,6 +54,16 @@ def _stats(args):
         lines.append("| %s | %s | %.2f | %.3f | %.1f |" % (
             r["Name"].split("(")[0][:90], r["Calls"], float(r["AverageNs"]) / 1e3,
             float(r["TotalDurationNs"]) / 1e6, 100 * float(r["TotalDurationNs"]) / tot))
+    if args.trace and args.tail_kernel:
+        # the launches bench.py times alone with HIP events are the last ones of the kernel
+        tr = sorted((r for r in csv.DictReader(open(args.trace)) if args.tail_kernel in r["Kernel_Name"]),
+                    key=lambda r: int(r["Start_Timestamp"]))
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr]
+        if d:
+            tail = d[-args.tail:]
+            lines += ["", "last %d launches of %s (the event-timed repetitions): avg %.2f us; all %d: avg %.2f us, "
+                      "min %.2f, max %.2f" % (len(tail), args.tail_kernel, sum(tail) / len(tail), len(d),
+                                                sum(d) / len(d), min(d), max(d))]
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
@@ -105,6 +115,9 @@ def main():
     s.add_argument("out")
     s.add_argument("--command", required=True)
     s.add_argument("--top", type=int, default=16)
+    s.add_argument("--trace", default=None, help="kernel_trace.csv of the same run")
+    s.add_argument("--tail-kernel", default=None, help="kernel name substring for the tail average")
+    s.add_argument("--tail", type=int, default=20)
     t = sub.add_parser("traffic")
     t.add_argument("out")
     t.add_argument("--kind", choices=sorted(KERNEL_SOURCES), required=True)
