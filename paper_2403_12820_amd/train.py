@@ -4,8 +4,10 @@ Python only sequences calls; every step runs in the HIP library:
   * trajectories: batched mass-spring steps (cloth_ms_step), frames saved every `stride` steps;
   * normalisation: RMS one-frame increments of x and v from the loss kernel;
   * minibatches: random (scene, frame) windows gathered on the device (pecnn_gather_windows);
-  * loss: data term of eq. (8) on the one-step prediction and on an 8-step unrolled prediction
-    (pecnn_loss_mse), alpha = 0;
+  * loss: eq. (8) on the one-step prediction and on an 8-step unrolled prediction
+    (pecnn_loss_mse): (1 - alpha) x the data term against the saved frames plus alpha x the
+    physics term, whose target is the simulator's velocity after the frame's `stride` steps from
+    the frame's own input state (cloth_ms_step), held constant in the backward pass;
   * gradients: back-propagation through the unrolled frames (pecnn_backward, BPTT);
   * update: Adam (pecnn_adam_step), lr 1e-3.
 
@@ -25,6 +27,8 @@ import numpy as np
 from . import inputs as I
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# a position scale whose inverse square is 0 in FP32: the loss then compares velocities only
+NO_POSITIONS = 1e30
 
 
 class Trajectories:
@@ -53,7 +57,7 @@ class Trajectories:
         from . import _lib as L
         n_free = int((self.batch.pin == 0).sum())
         acc = torch.zeros(2, dtype=torch.float64, device=self.frames.device)
-        big = 1e30
+        big = NO_POSITIONS
         for f in range(self.n_frames - 1):
             # with the other scale huge, the loss value is the mean squared increment of one field
             L.pecnn_loss_mse(self.plan, self.frames[f + 1], self.frames[f], 1.0, big, 1.0, n_free, acc[0:1], None)
@@ -113,7 +117,7 @@ class Trainer:
         self.model = L.make_model(self.theta, ch, L.PECNN_FP32, dt=dt_nn)
         self.device = device
 
-    def _buffers(self, plan, U, N):
+    def _buffers(self, plan, U, N, phys=False):
         import torch
         from . import _lib as L
         if getattr(self, "_N", None) != (U, N):
@@ -123,50 +127,79 @@ class Trainer:
             self.loss = torch.zeros(1, dtype=torch.float64, device=self.device)
             self.ws_r = plan.workspace(L.WS_REDUCE)
             self.ws_b = plan.workspace(L.WS_BACKWARD, self.model)
+            self.phys = None
+        if phys and self.phys is None:
+            self.phys = torch.empty(U, 6, N, device=self.device)
+            self.ws_m = plan.workspace(L.WS_MS_STEP)
 
-    def step(self, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0, lr=None):
-        """One iteration: unrolled forward, loss, BPTT, Adam. Returns the loss (device scalar)."""
+    def gradient(self, buf, plan, n_free, sx, sv, one_step_weight=1.0, alpha=0.0, sim=None, stride=10):
+        """Loss and theta gradient (self.loss, self.g) of the unrolled prediction from buf[0], buf[1]
+        (S^{k-1}, S^k) against buf[2:] (the next saved frames), by BPTT."""
         from . import _lib as L
-        U = wb.n_unroll
-        N = wb.n_win * wb.npw
-        self._buffers(plan, U, N)
+        if not 0.0 <= alpha <= 1.0 or (alpha > 0.0 and sim is None):
+            raise ValueError("alpha must lie in [0, 1]; the physics term needs the simulator parameters")
+        U, N = buf.shape[0] - 2, buf.shape[2]
+        self._buffers(plan, U, N, alpha > 0.0)
         pred, grads = self.pred, self.grads
-        S = [wb.buf[0], wb.buf[1]]  # S^{k-1}, S^k (ground truth)
+        S = [buf[0], buf[1]]
         for t in range(U):
             L.pecnn_forward(plan, self.model, S[-2], S[-1], pred[t])
+            if alpha > 0.0:
+                # physics target of eq. (8): the simulator's frame from this frame's input state
+                L.cloth_ms_step(plan, sim, S[-1], self.phys[t], stride, ws=self.ws_m)
             S.append(pred[t])
         self.loss.zero_()
         grads.zero_()
         for t in range(U):
             # l_8: mean over the unrolled frames; l_1: the first frame once more
             w = 1.0 / U + (one_step_weight if t == 0 else 0.0)
-            L.pecnn_loss_mse(plan, pred[t], wb.buf[t + 2], sx, sv, w, n_free, self.loss, grads[t], ws=self.ws_r)
+            if alpha < 1.0:
+                L.pecnn_loss_mse(plan, pred[t], buf[t + 2], sx, sv, (1.0 - alpha) * w, n_free, self.loss, grads[t],
+                                 ws=self.ws_r)
+            if alpha > 0.0:
+                # impulses only: the position planes get a vanishing weight
+                L.pecnn_loss_mse(plan, pred[t], self.phys[t], NO_POSITIONS, sv, alpha * w, n_free, self.loss,
+                                 grads[t], ws=self.ws_r)
         self.g.zero_()
         for t in range(U - 1, -1, -1):
             # pred[t] = f(S[t], S[t+1]); S[t+2] = pred[t]; only predicted frames carry gradients
             g_cur = grads[t - 1] if t >= 1 else None
             g_prev = grads[t - 2] if t >= 2 else None
             L.pecnn_backward(plan, self.model, S[t], S[t + 1], grads[t], g_cur, g_prev, self.g, ws=self.ws_b)
+        return self.loss
+
+    def step(self, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0, lr=None, alpha=0.0, sim=None,
+             stride=10):
+        """One iteration: unrolled forward, loss, BPTT, Adam. Returns the loss (device scalar)."""
+        from . import _lib as L
+        self.gradient(wb.buf, plan, n_free, sx, sv, one_step_weight, alpha, sim, stride)
         self.t += 1
         L.pecnn_adam_step(self.theta, self.m, self.v, self.g, self.t, lr=self.lr if lr is None else lr)
         return self.loss
 
 
-def eval_loss(tr: Trainer, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0):
+def eval_loss(tr: Trainer, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0, alpha=0.0, sim=None,
+              stride=10):
     """The training loss of the current theta on the windows already gathered in wb (no update)."""
     import torch
     from . import _lib as L
     U = wb.n_unroll
     N = wb.n_win * wb.npw
     pred = torch.empty(U, 6, N, device=tr.device)
+    phys = torch.empty(6, N, device=tr.device) if alpha > 0.0 else None
+    ws_m = plan.workspace(L.WS_MS_STEP) if alpha > 0.0 else None
     S = [wb.buf[0], wb.buf[1]]
     loss = torch.zeros(1, dtype=torch.float64, device=tr.device)
     ws_r = plan.workspace(L.WS_REDUCE)
     for t in range(U):
         L.pecnn_forward(plan, tr.model, S[-2], S[-1], pred[t])
-        S.append(pred[t])
         w = 1.0 / U + (one_step_weight if t == 0 else 0.0)
-        L.pecnn_loss_mse(plan, pred[t], wb.buf[t + 2], sx, sv, w, n_free, loss, None, ws=ws_r)
+        if alpha < 1.0:
+            L.pecnn_loss_mse(plan, pred[t], wb.buf[t + 2], sx, sv, (1.0 - alpha) * w, n_free, loss, None, ws=ws_r)
+        if alpha > 0.0:
+            L.cloth_ms_step(plan, sim, S[-1], phys, stride, ws=ws_m)
+            L.pecnn_loss_mse(plan, pred[t], phys, NO_POSITIONS, sv, alpha * w, n_free, loss, None, ws=ws_r)
+        S.append(pred[t])
     return float(loss.item())
 
 
@@ -200,9 +233,10 @@ def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0,
 
 
 def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=32, lr=1e-3, seed=4,
-          n_frames=201, stride=10, log_every=500, eval_frames=100, device="cuda", verbose=True, lr_final=None):
+          n_frames=201, stride=10, log_every=500, eval_frames=100, device="cuda", verbose=True, lr_final=None,
+          alpha=0.0):
     """Adam at lr, annealed along a cosine to lr_final over the run when lr_final is given (the
-    post-process cosine schedule of Table 1)."""
+    post-process cosine schedule of Table 1); alpha weighs the physics term of eq. (8)."""
     import torch
     mat = I.Material()
     t0 = time.time()
@@ -225,10 +259,10 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     for it in range(1, iters + 1):
         plan, n_free = wb.sample(rng)
         lr_t = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (it - 1) / iters))
-        loss = tr.step(wb, plan, n_free, sx, sv, lr=lr_t)
+        loss = tr.step(wb, plan, n_free, sx, sv, lr=lr_t, alpha=alpha, sim=traj.sim, stride=stride)
         if it % log_every == 0 or it == 1 or it == iters:
             lv = float(loss.item())
-            vl = eval_loss(tr, wv, val_plan, val_free, sx, sv)
+            vl = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
             curve.append((it, lv, vl))
             if not np.isfinite(lv):
                 raise FloatingPointError("training diverged at iteration %d" % it)
@@ -245,12 +279,13 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     theta_best = best[1]
     rms_trained, _ = rollout_rms(traj, val_ids, theta_best, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
     rms_untrained, _ = rollout_rms(traj, val_ids, theta0, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
-    val_loss_final = eval_loss(tr, wv, val_plan, val_free, sx, sv)
+    val_loss_final = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
     tr.theta.copy_(torch.tensor(theta_best, device=device))
-    val_loss_best = eval_loss(tr, wv, val_plan, val_free, sx, sv)
+    val_loss_best = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
     report = {
         "scenes": n_scenes, "grid": size, "val_scenes": n_val, "iters": iters, "minibatch": n_win,
-        "unroll": n_unroll, "channels": ch, "lr": lr, "lr_final": lr_final, "stride": stride, "frames": n_frames,
+        "unroll": n_unroll, "channels": ch, "lr": lr, "lr_final": lr_final, "alpha": alpha, "stride": stride,
+        "frames": n_frames,
         "increment_scales": [sx, sv], "loss_curve": curve, "generation_s": t_gen, "train_s": t_train,
         "val_rms_trained": rms_trained.tolist(), "val_rms_untrained": rms_untrained.tolist(),
         "val_rms_trained_mean": float(rms_trained.mean()), "val_rms_untrained_mean": float(rms_untrained.mean()),
@@ -272,12 +307,13 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=None)
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--alpha", type=float, default=0.0, help="weight of the physics term of eq. (8)")
     ap.add_argument("--log-every", type=int, default=500)
     ap.add_argument("--out", default=os.path.join(HERE, "weights", "pecnn_ch32.npy"))
     ap.add_argument("--report", default=None)
     args = ap.parse_args()
     theta, report = train(args.scenes, args.size, args.val, args.iters, args.minibatch, args.unroll, args.ch,
-                          args.lr, args.seed, log_every=args.log_every, lr_final=args.lr_final)
+                          args.lr, args.seed, log_every=args.log_every, lr_final=args.lr_final, alpha=args.alpha)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, theta.astype(np.float32), allow_pickle=False)
     rep = args.report or os.path.splitext(args.out)[0] + "_report.json"

@@ -92,6 +92,71 @@ def test_bptt_gradient_matches_oracle(L, unroll):
     assert rel_inf(gth.cpu().numpy(), ogt) <= 1e-3, rel_inf(gth.cpu().numpy(), ogt)
 
 
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 1.0])
+def test_trainer_gradient_with_physics_term_matches_oracle(L, alpha):
+    """Eq. (8) with both terms: (1 - alpha) x the data term plus alpha x the physics term, whose
+    target is the simulator's velocity after one frame (10 steps) from each frame's own input state,
+    held constant. The trainer's loss and theta gradient over a 3-frame unroll equal the oracle's
+    chain, which runs its own FP64 simulator for the targets."""
+    import torch
+    from paper_2403_12820_amd.train import NO_POSITIONS, Trainer
+    ch, dt, stride, U = 16, 5e-3, 10, 3
+    scenes = I.random_scenes([(8, 8), (6, 10)], seed=11)
+    batch = I.make_batch(scenes)
+    s1 = batch.state.astype(np.float64)
+    s1[3:] = I.random_array((3, batch.total), seed=12, scale=0.1)
+    s0 = s1.copy()
+    s0[:3] -= dt * s1[3:]
+    targets = [s1 + I.random_array(s1.shape, seed=20 + t, scale=0.01) for t in range(U)]
+    th = (I.init_theta(ch, seed=13).astype(np.float64) * 10).astype(np.float32)
+    sx, sv = 0.01, 0.05
+    n_free = int((batch.pin == 0).sum())
+    plan = L.Plan.from_batch(batch)
+    tr = Trainer(ch=ch, dt_nn=dt, theta=th)
+    frames = np.stack([s0, s1] + targets).astype(np.float32)
+    tr.gradient(torch.tensor(frames, device="cuda"), plan, n_free, sx, sv, 1.0, alpha, L.ms_params(MAT), stride)
+    torch.cuda.synchronize()
+    loss, gth = tr.loss.item(), tr.g.cpu().numpy()
+
+    th64 = th.astype(np.float64)
+    states = [frames[0].astype(np.float64), frames[1].astype(np.float64)]
+    og = [None, None] + [np.zeros_like(s0) for _ in range(U)]
+    lv = 0.0
+    for t in range(U):
+        sn, _ = oracle.batch_cnn_forward(batch, ch, 1.0, dt, th64, states[-2], states[-1])
+        phys = oracle.batch_ms_step(batch, states[-1], MAT, stride)
+        states.append(sn)
+        w = 1.0 / U + (1.0 if t == 0 else 0.0)
+        for tgt, sxx, wt in ((frames[t + 2].astype(np.float64), sx, (1 - alpha) * w), (phys, NO_POSITIONS, alpha * w)):
+            if wt > 0:
+                v, g = oracle.loss_mse(batch.pin, n_free, sxx, sv, wt, sn, tgt)
+                lv += v
+                og[t + 2] += g
+    ogt = np.zeros(th.size)
+    for t in range(U - 1, -1, -1):
+        gc, gp, gt = oracle.batch_cnn_backward(batch, ch, 1.0, dt, th64, states[t], states[t + 1], og[t + 2])
+        if t >= 1:
+            og[t + 1] += gc
+        if t >= 2:
+            og[t] += gp
+        ogt += gt
+    assert abs(loss - lv) <= 1e-5 * abs(lv), (loss, lv)
+    assert rel_inf(gth, ogt) <= 1e-3, rel_inf(gth, ogt)
+
+
+def test_trainer_rejects_bad_alpha(L):
+    from paper_2403_12820_amd.train import Trainer
+    import torch
+    tr = Trainer(ch=16, dt_nn=5e-3)
+    batch = I.make_batch(I.random_scenes([(8, 8)], seed=1))
+    plan = L.Plan.from_batch(batch)
+    buf = torch.zeros(3, 6, batch.total, device="cuda")
+    with pytest.raises(ValueError):
+        tr.gradient(buf, plan, 10, 0.01, 0.05, alpha=1.5, sim=L.ms_params(MAT))
+    with pytest.raises(ValueError):
+        tr.gradient(buf, plan, 10, 0.01, 0.05, alpha=0.5, sim=None)
+
+
 def test_training_reduces_loss_and_beats_untrained(L):
     """A short training run on small synthetic trajectories lowers the loss and the 20-frame
     rollout error of held-out scenes compared with the untrained network."""

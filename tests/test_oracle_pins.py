@@ -552,6 +552,21 @@ def test_loss_special_values_and_gradient():
         assert abs(fd - g[c, p]) < 1e-7
 
 
+def test_loss_physics_term_compares_velocities_only():
+    """The physics term of eq. (8) compares impulses, i.e. velocities: with the position scale at
+    1e30 the position error of 0.2 adds nothing (to value and gradient) and the value is the
+    velocity error alone."""
+    n = 10
+    pin = np.zeros(n, np.uint8)
+    st = I.random_array((6, n), seed=91)
+    sh = st.copy()
+    sh[0, 3] += 0.2
+    sh[4, 5] -= 0.5
+    val, g = oracle.loss_mse(pin, n, 1e30, 2.0, 1.0, sh, st)
+    assert abs(val - (0.5 / 2.0) ** 2 / n) < 1e-15
+    assert np.abs(g[:3]).max() < 1e-40 and abs(g[4, 5] - 2 * (-0.5) / 4.0 / n) < 1e-15
+
+
 def test_p11_adam_first_step_and_steady_gradient():
     """Step 1: m_hat = g, v_hat = g^2, so the update is -lr g/(|g| + eps). A constant gradient
     keeps m_hat = g and v_hat = g^2 at every step, so the update stays the same."""
