@@ -74,6 +74,18 @@ int64_t pecnn_plan_nodes(const pecnn_plan* plan);   /* N_total, or -1 for a null
 int pecnn_plan_set_tiles(pecnn_plan* plan, int32_t ms_cfg, int32_t cnn_cfg);
 int pecnn_plan_get_tiles(const pecnn_plan* plan, int32_t* ms_cfg, int32_t* cnn_cfg);
 
+/* Uniform pressure p_b of eq. (3) per instance, N/m^2 (host float [n], finite; 0 = none, the
+   default of a new plan). On every node the four nearest neighbours are taken round it in the
+   order right (0,+1), down (+1,0), left (0,-1), up (-1,0); each consecutive pair (j1, j2)
+   whose two nodes lie on the grid adds p_b (x_j1 - x_i) x (x_j2 - x_i), so on the flat rest
+   grid X = (j h, i h, 0) p_b > 0 pushes along +z. The mass-spring step adds it to the force;
+   the CNN frames add it at the positions of S^k as a known external force,
+   dt p_b / m sum_pairs (...), next to the wind (pecnn_forward, pecnn_backward, pecnn_rollout).
+   The rollout guard's energy check is off for instances with p_b != 0 (pressure does work).
+   Copies the values into the plan's device records (synchronous on `stream`); drops the
+   rollout's cached graphs when the set of kernels changes. */
+int pecnn_plan_set_pressure(pecnn_plan* plan, const float* pressure, void* stream);
+
 /* ------------------------------------------------------------------ mass-spring step */
 
 /* Material and integration parameters of the mass-spring model (section 3.1). */
@@ -85,8 +97,9 @@ typedef struct {
   float dt;                        /* time step of eq. (5), > 0 */
 } cloth_ms_params;
 
-/* n_steps >= 1 steps of the mass-spring cloth (section 3.1, eqs. 1, 2, 4, 5):
+/* n_steps >= 1 steps of the mass-spring cloth (section 3.1, eqs. 1, 2, 3, 4, 5):
      f_i = m (g + a_ext) - d v_i + sum_j [ -k_j (r - L_j) x_ij/r - mu ((v_ij . x_ij)/r^2) x_ij ]
+           + the pressure force of eq. (3) (pecnn_plan_set_pressure)
    over the 12 springs of the 13-point stencil (8 nodes of the 3x3 block, 4 nodes two steps
    away in the cardinal directions; springs exist only inside the grid), x_ij = x_i - x_j,
    r = |x_ij|, then v' = C(v + dt f/m), x' = x + dt v' with C zeroing pinned velocities.
@@ -120,7 +133,8 @@ int64_t pecnn_theta_size(int32_t ch);
      U(S)[c][o] = S_c(clamp(p+o)) - [c < 3] S_c(p)    (o in {-1,0,1}^2, clamp-to-edge)
      phi = K U(S^k),  xi = K U(S^k - S^{k-1})                            (eq. 6)
      dv = W_L phi + b_L + W_N sigma((A phi) * (B phi)) + W_D (xi * sigma(phi))   (eq. 7)
-     v^{k+1} = C(v^k + dv + dt a_ext),  x^{k+1} = x^k + dt v^{k+1}      (eq. 5)
+     v^{k+1} = C(v^k + dv + dt a_ext + dt f_p(x^k) / m),  x^{k+1} = x^k + dt v^{k+1}   (eq. 5)
+   with f_p the pressure force of eq. (3) (zero unless pecnn_plan_set_pressure set one).
    s_prev = S^{k-1}, s_cur = S^k, s_next = S^{k+1}: device [6][N_total]; s_next must not overlap
    the inputs. No workspace. */
 int pecnn_forward(const pecnn_plan* plan, const pecnn_model* model, const float* s_prev,
@@ -140,7 +154,8 @@ int pecnn_backward(const pecnn_plan* plan, const pecnn_model* model, const float
 
 /* Guard of the learned rollout. Every check_every network steps each active instance is
    checked: if its largest structural stretch ratio r/L exceeds stretch_max, or its energy
-   gain (E_now - E_start)/E_ref exceeds energy_gain_max (E_ref = total mass |g| (W-1) h), the
+   gain (E_now - E_start)/E_ref exceeds energy_gain_max (E_ref = total mass |g| (W-1) h; no
+   energy check for instances with a pressure, which does work on the cloth), the
    instance falls back for good to the mass-spring step with 'substeps' steps of sim->dt per
    network step (substeps * sim->dt should equal model->dt). check_every <= 0 disables it. */
 typedef struct {

@@ -8,8 +8,9 @@ compiles it with gcc and marshals numpy arrays through ctypes. Every function
 works on one cloth instance at a time; the batch helpers loop over instances.
 
 Paper passages followed (section / equation):
-  ms_force, ms_step, ms_run  - section 3.1, eqs. (1), (2), (4), (5)
-  cnn_forward                - section 3.2, eqs. (6), (7), then (5) (Fig. 2)
+  ms_force, ms_step, ms_run  - section 3.1, eqs. (1), (2), (3), (4), (5)
+  cnn_forward                - section 3.2, eqs. (6), (7), then (5) (Fig. 2), with wind and the
+                               pressure of eq. (3) as known external forces
   cnn_backward               - section 3.2.1, reverse mode of the above
   loss_mse                   - eq. (8), data term
   adam                       - Table 1 (optimizer Adam)
@@ -47,9 +48,9 @@ def _load():
             build(force=True)
         _lib = C.CDLL(_LIB)
         d, i, l, p = C.c_double, C.c_int, C.c_long, C.c_void_p
-        _lib.or_ms_force.argtypes = [i, i, d, d, p, p, p, p, p]
-        _lib.or_ms_step.argtypes = [i, i, d, d, p, p, p, p, p]
-        _lib.or_ms_run.argtypes = [i, i, d, d, p, p, p, p, i]
+        _lib.or_ms_force.argtypes = [i, i, d, d, p, d, p, p, p, p]
+        _lib.or_ms_step.argtypes = [i, i, d, d, p, d, p, p, p, p]
+        _lib.or_ms_run.argtypes = [i, i, d, d, p, d, p, p, p, i]
         _lib.or_energy.argtypes = [i, i, d, d, p, p, p]
         _lib.or_energy.restype = d
         _lib.or_max_stretch.argtypes = [i, i, d, p, i]
@@ -58,8 +59,8 @@ def _load():
         _lib.or_sq_pos_err.restype = d
         _lib.or_theta_size.argtypes = [i]
         _lib.or_theta_size.restype = l
-        _lib.or_cnn_forward.argtypes = [i, i, i, d, d, p, p, p, p, p, p, i, p]
-        _lib.or_cnn_backward.argtypes = [i, i, i, d, d, p, p, p, p, p, p, p, p]
+        _lib.or_cnn_forward.argtypes = [i, i, i, d, d, p, d, p, p, p, p, p, i, p]
+        _lib.or_cnn_backward.argtypes = [i, i, i, d, d, d, p, p, p, p, p, p, p, p]
         _lib.or_loss_mse.argtypes = [l, p, l, d, d, d, p, p, p]
         _lib.or_loss_mse.restype = d
         _lib.or_adam.argtypes = [l, d, d, d, d, i, p, p, p, p]
@@ -92,26 +93,26 @@ def ms_params(mat, dt=None) -> _MsParams:
     return p
 
 
-def ms_force(H, W, h, m, a_ext, pin, s, mat):
+def ms_force(H, W, h, m, a_ext, pin, s, mat, pressure=0.0):
     s = _f64(s).reshape(6, H * W)
     f = np.zeros((3, H * W))
     a, pn, P = _f64(a_ext), _u8(pin), ms_params(mat)
-    _load().or_ms_force(H, W, h, m, _ptr(a), C.byref(P), _ptr(pn), _ptr(s), _ptr(f))
+    _load().or_ms_force(H, W, h, m, _ptr(a), float(pressure), C.byref(P), _ptr(pn), _ptr(s), _ptr(f))
     return f
 
 
-def ms_step(H, W, h, m, a_ext, pin, s, mat, dt=None):
+def ms_step(H, W, h, m, a_ext, pin, s, mat, dt=None, pressure=0.0):
     s = _f64(s).reshape(6, H * W)
     out = np.empty_like(s)
     a, pn, P = _f64(a_ext), _u8(pin), ms_params(mat, dt)
-    _load().or_ms_step(H, W, h, m, _ptr(a), C.byref(P), _ptr(pn), _ptr(s), _ptr(out))
+    _load().or_ms_step(H, W, h, m, _ptr(a), float(pressure), C.byref(P), _ptr(pn), _ptr(s), _ptr(out))
     return out
 
 
-def ms_run(H, W, h, m, a_ext, pin, s, mat, n_steps, dt=None):
+def ms_run(H, W, h, m, a_ext, pin, s, mat, n_steps, dt=None, pressure=0.0):
     s = _f64(s).reshape(6, H * W).copy()
     a, pn, P = _f64(a_ext), _u8(pin), ms_params(mat, dt)
-    _load().or_ms_run(H, W, h, m, _ptr(a), C.byref(P), _ptr(pn), _ptr(s), int(n_steps))
+    _load().or_ms_run(H, W, h, m, _ptr(a), float(pressure), C.byref(P), _ptr(pn), _ptr(s), int(n_steps))
     return s
 
 
@@ -135,24 +136,25 @@ def theta_size(ch) -> int:
     return int(_load().or_theta_size(ch))
 
 
-def cnn_forward(H, W, ch, alpha, dt, a_ext, pin, theta, s_prev, s_cur, emu=0):
-    """Returns (s_next [6, n], dv [3, n]). emu: bf16 operand-rounding flags (0 = exact FP64)."""
+def cnn_forward(H, W, ch, alpha, dt, a_ext, pin, theta, s_prev, s_cur, emu=0, pm=0.0):
+    """Returns (s_next [6, n], dv [3, n]). emu: bf16 operand-rounding flags (0 = exact FP64);
+    pm: pressure per unit node mass (eq. 3 force / m)."""
     sp, sc = _f64(s_prev).reshape(6, H * W), _f64(s_cur).reshape(6, H * W)
     th, a, pn = _f64(theta), _f64(a_ext), _u8(pin)
     assert th.size == theta_size(ch) and ch <= 64
     out = np.empty((6, H * W))
     dv = np.empty((3, H * W))
-    _load().or_cnn_forward(H, W, ch, alpha, dt, _ptr(a), _ptr(pn), _ptr(th), _ptr(sp), _ptr(sc),
+    _load().or_cnn_forward(H, W, ch, alpha, dt, _ptr(a), float(pm), _ptr(pn), _ptr(th), _ptr(sp), _ptr(sc),
                            _ptr(out), int(emu), _ptr(dv))
     return out, dv
 
 
-def cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev, s_cur, g_next):
+def cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev, s_cur, g_next, pm=0.0):
     """Returns (g_cur, g_prev, g_theta) for g_next = dLoss/dS^{k+1}."""
     sp, sc, gn = (_f64(x).reshape(6, H * W) for x in (s_prev, s_cur, g_next))
     th, pn = _f64(theta), _u8(pin)
     gc, gp, gt = np.zeros((6, H * W)), np.zeros((6, H * W)), np.zeros(th.size)
-    _load().or_cnn_backward(H, W, ch, alpha, dt, _ptr(pn), _ptr(th), _ptr(sp), _ptr(sc), _ptr(gn),
+    _load().or_cnn_backward(H, W, ch, alpha, dt, float(pm), _ptr(pn), _ptr(th), _ptr(sp), _ptr(sc), _ptr(gn),
                             _ptr(gc), _ptr(gp), _ptr(gt))
     return gc, gp, gt
 
@@ -179,13 +181,18 @@ def _inst(batch, b):
             np.asarray(batch.a_ext[b], np.float64), batch.pin[batch.instance(b)])
 
 
+def _pressure(batch, b):
+    p = getattr(batch, "pressure", None)
+    return 0.0 if p is None else float(p[b])
+
+
 def batch_ms_step(batch, s, mat, n_steps=1, dt=None):
     s = _f64(s)
     out = np.empty_like(s)
     for b in range(batch.n):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
-        out[:, sl] = ms_run(H, W, h, m, a, pin, s[:, sl], mat, n_steps, dt)
+        out[:, sl] = ms_run(H, W, h, m, a, pin, s[:, sl], mat, n_steps, dt, _pressure(batch, b))
     return out
 
 
@@ -197,7 +204,7 @@ def batch_cnn_forward(batch, ch, alpha, dt, theta, s_prev, s_cur, emu=0):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
         out[:, sl], dv[:, sl] = cnn_forward(H, W, ch, alpha, dt, a, pin, theta, s_prev[:, sl],
-                                            s_cur[:, sl], emu)
+                                            s_cur[:, sl], emu, _pressure(batch, b) / m)
     return out, dv
 
 
@@ -208,7 +215,8 @@ def batch_cnn_backward(batch, ch, alpha, dt, theta, s_prev, s_cur, g_next):
     for b in range(batch.n):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
-        c, p, t = cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev[:, sl], s_cur[:, sl], g_next[:, sl])
+        c, p, t = cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev[:, sl], s_cur[:, sl], g_next[:, sl],
+                               _pressure(batch, b) / m)
         gc[:, sl] += c
         gp[:, sl] += p
         gt += t

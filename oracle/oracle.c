@@ -8,12 +8,14 @@
  * Plain loops in double precision, one cloth instance per call, written in the
  * order the paper states each step:
  *   - mass-spring step: section 3.1, eqs. (1) elastic spring force, (2) spring
- *     damping, (4) gravity and air drag, (5) semi-implicit Euler with the
- *     constraint operator (Dirichlet pins);
+ *     damping, (3) uniform pressure on the four nearest neighbours, (4) gravity
+ *     and air drag, (5) semi-implicit Euler with the constraint operator
+ *     (Dirichlet pins);
  *   - physics-embedded CNN cell: section 3.2, eq. (6) one shared convolution
  *     applied to the state and to its time derivative, eq. (7) linear, nonlinear
  *     (ISRU) and derivative branches summed into a velocity increment, then
- *     eq. (5) again as the embedded integrator (Fig. 2);
+ *     eq. (5) again as the embedded integrator (Fig. 2), with wind and the
+ *     pressure of eq. (3) added as known external forces;
  *   - its exact reverse mode (section 3.2.1: gradient backpropagation), the
  *     data term of the eq. (8) loss and Adam (Table 1);
  *   - FP64 diagnostics: position RMS error, energy, stretch ratio.
@@ -47,10 +49,36 @@ typedef struct {
 
 static double or_dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+/* Eq. (3): pressure on node (i, j) from its four nearest neighbours. Going round the node
+   through right (0,+1), down (+1,0), left (0,-1) and up (-1,0), every consecutive pair
+   (j1, j2) whose two nodes lie on the grid adds pr (x_j1 - x_i) x (x_j2 - x_i). With rows
+   running down the grid this is the clockwise order, and on the flat rest grid
+   X = (j h, i h, 0) each pair gives +h^2 along z, so pr > 0 pushes along +z (against
+   gravity). Adds scale * force to F. */
+static void or_pressure(int H, int W, const double *s, int i, int j, double scale, double *F)
+{
+    static const int R[4][2] = {{0, 1}, {1, 0}, {0, -1}, {-1, 0}};
+    const long n = (long)H * W, p = (long)i * W + j;
+    for (int k = 0; k < 4; ++k) {
+        const int i1 = i + R[k][0], j1 = j + R[k][1];
+        const int i2 = i + R[(k + 1) % 4][0], j2 = j + R[(k + 1) % 4][1];
+        if (i1 < 0 || i1 >= H || j1 < 0 || j1 >= W || i2 < 0 || i2 >= H || j2 < 0 || j2 >= W) continue;
+        double a[3], b[3];
+        for (int c = 0; c < 3; ++c) {
+            a[c] = s[c * n + (long)i1 * W + j1] - s[c * n + p];
+            b[c] = s[c * n + (long)i2 * W + j2] - s[c * n + p];
+        }
+        F[0] += scale * (a[1] * b[2] - a[2] * b[1]);
+        F[1] += scale * (a[2] * b[0] - a[0] * b[2]);
+        F[2] += scale * (a[0] * b[1] - a[1] * b[0]);
+    }
+}
+
 /* Total force on each node, f[3][H*W]; pinned nodes get zero.
    f_i = m (g + a_ext) - d v_i + sum_j [ -k_j (r - L_j) x_ij / r - mu ((v_ij . x_ij)/r^2) x_ij ]
+         + f_p,i (eq. 3, pressure pr)
    with x_ij = x_i - x_j, v_ij = v_i - v_j, r = |x_ij|. */
-void or_ms_force(int H, int W, double h, double m, const double *a_ext, const or_ms_params *P,
+void or_ms_force(int H, int W, double h, double m, const double *a_ext, double pr, const or_ms_params *P,
                  const uint8_t *pin, const double *s, double *f)
 {
     const long n = (long)H * W;
@@ -78,18 +106,19 @@ void or_ms_force(int H, int W, double h, double m, const double *a_ext, const or
                     const double cd = -P->mu * or_dot3(vij, xij) / (r * r); /* eq. (2) */
                     for (int a = 0; a < 3; ++a) F[a] += (ce + cd) * xij[a];
                 }
+                if (pr != 0.0) or_pressure(H, W, s, i, j, pr, F);
             }
             for (int a = 0; a < 3; ++a) f[a * n + p] = F[a];
         }
 }
 
 /* One step of eq. (5): v' = C(v + dt f / m), x' = x + dt v'; C zeroes pinned velocities. */
-void or_ms_step(int H, int W, double h, double m, const double *a_ext, const or_ms_params *P,
+void or_ms_step(int H, int W, double h, double m, const double *a_ext, double pr, const or_ms_params *P,
                 const uint8_t *pin, const double *s, double *out)
 {
     const long n = (long)H * W;
     double *f = (double *)malloc(sizeof(double) * 3 * n);
-    or_ms_force(H, W, h, m, a_ext, P, pin, s, f);
+    or_ms_force(H, W, h, m, a_ext, pr, P, pin, s, f);
     for (long p = 0; p < n; ++p)
         for (int a = 0; a < 3; ++a) {
             const double v = pin[p] ? 0.0 : s[(3 + a) * n + p] + P->dt * f[a * n + p] / m;
@@ -100,13 +129,13 @@ void or_ms_step(int H, int W, double h, double m, const double *a_ext, const or_
 }
 
 /* n_steps consecutive steps; s is overwritten with the final state. */
-void or_ms_run(int H, int W, double h, double m, const double *a_ext, const or_ms_params *P,
+void or_ms_run(int H, int W, double h, double m, const double *a_ext, double pr, const or_ms_params *P,
                const uint8_t *pin, double *s, int n_steps)
 {
     const long n = (long)H * W;
     double *t = (double *)malloc(sizeof(double) * 6 * n);
     for (int k = 0; k < n_steps; ++k) {
-        or_ms_step(H, W, h, m, a_ext, P, pin, s, t);
+        or_ms_step(H, W, h, m, a_ext, pr, P, pin, s, t);
         memcpy(s, t, sizeof(double) * 6 * n);
     }
     free(t);
@@ -316,8 +345,10 @@ static double *or_time_diff(long n, const double *sp, const double *sk, int emu)
 }
 
 /* One frame of the framework (Fig. 2): the cell gives dv, then eq. (5) with the pins and the
-   hard-encoded wind: v' = C(v + dv + dt a_ext), x' = x + dt v'. */
-void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double *a_ext,
+   hard-encoded external forces, wind and pressure (eq. 3 at the positions of S^k, per unit
+   mass pm = pr / m): v' = C(v + dv + dt a_ext + dt pm sum_pairs (x_j1 - x) x (x_j2 - x)),
+   x' = x + dt v'. */
+void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double *a_ext, double pm,
                     const uint8_t *pin, const double *theta, const double *s_prev,
                     const double *s_cur, double *s_next, int emu, double *dv_out)
 {
@@ -329,9 +360,11 @@ void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double 
         for (int j = 0; j < W; ++j) {
             const long p = (long)i * W + j;
             or_cell_node(H, W, ch, alpha, theta, &Lo, s_cur, dS, i, j, emu, o);
+            double fp[3] = {0.0, 0.0, 0.0};
+            if (pm != 0.0) or_pressure(H, W, s_cur, i, j, dt * pm, fp);
             for (int a = 0; a < 3; ++a) {
                 if (dv_out) dv_out[a * n + p] = o->dv[a];
-                const double v = pin[p] ? 0.0 : s_cur[(3 + a) * n + p] + o->dv[a] + dt * a_ext[a];
+                const double v = pin[p] ? 0.0 : s_cur[(3 + a) * n + p] + o->dv[a] + dt * a_ext[a] + fp[a];
                 s_next[(3 + a) * n + p] = v;
                 s_next[a * n + p] = s_cur[a * n + p] + dt * v;
             }
@@ -342,7 +375,7 @@ void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double 
 
 /* Reverse mode of or_cnn_forward (emu = 0). Given g_next = dLoss/dS^{k+1}, accumulate
    dLoss/dS^k into g_cur, dLoss/dS^{k-1} into g_prev and dLoss/dtheta into g_theta. */
-void or_cnn_backward(int H, int W, int ch, double alpha, double dt, const uint8_t *pin,
+void or_cnn_backward(int H, int W, int ch, double alpha, double dt, double pm, const uint8_t *pin,
                      const double *theta, const double *s_prev, const double *s_cur,
                      const double *g_next, double *g_cur, double *g_prev, double *g_theta)
 {
@@ -361,6 +394,32 @@ void or_cnn_backward(int H, int W, int ch, double alpha, double dt, const uint8_
                 g_cur[a * n + p] += g_next[a * n + p];
                 gdv[a] = pin[p] ? 0.0 : gvt;
                 g_cur[(3 + a) * n + p] += gdv[a];
+            }
+            /* pressure term c (x_j1 - x) x (x_j2 - x), c = dt pm: with A = x_j1 - x, B = x_j2 - x and
+               the adjoint gdv, d/dx_j1 = c B x gdv, d/dx_j2 = c gdv x A, d/dx = minus both */
+            if (pm != 0.0) {
+                static const int R[4][2] = {{0, 1}, {1, 0}, {0, -1}, {-1, 0}};
+                const double c = dt * pm;
+                for (int k = 0; k < 4; ++k) {
+                    const int i1 = i + R[k][0], j1 = j + R[k][1];
+                    const int i2 = i + R[(k + 1) % 4][0], j2 = j + R[(k + 1) % 4][1];
+                    if (i1 < 0 || i1 >= H || j1 < 0 || j1 >= W || i2 < 0 || i2 >= H || j2 < 0 || j2 >= W) continue;
+                    const long q1 = (long)i1 * W + j1, q2 = (long)i2 * W + j2;
+                    double A[3], B[3];
+                    for (int a = 0; a < 3; ++a) {
+                        A[a] = s_cur[a * n + q1] - s_cur[a * n + p];
+                        B[a] = s_cur[a * n + q2] - s_cur[a * n + p];
+                    }
+                    const double g1[3] = {c * (B[1] * gdv[2] - B[2] * gdv[1]), c * (B[2] * gdv[0] - B[0] * gdv[2]),
+                                          c * (B[0] * gdv[1] - B[1] * gdv[0])};
+                    const double g2[3] = {c * (gdv[1] * A[2] - gdv[2] * A[1]), c * (gdv[2] * A[0] - gdv[0] * A[2]),
+                                          c * (gdv[0] * A[1] - gdv[1] * A[0])};
+                    for (int a = 0; a < 3; ++a) {
+                        g_cur[a * n + q1] += g1[a];
+                        g_cur[a * n + q2] += g2[a];
+                        g_cur[a * n + p] -= g1[a] + g2[a];
+                    }
+                }
             }
             /* eq. (7) heads */
             for (int c = 0; c < ch; ++c) { gphi[c] = 0.0; gnn[c] = 0.0; gdd[c] = 0.0; }

@@ -63,6 +63,7 @@ def lib():
         "pecnn_plan_nodes": ([vp], i64),
         "pecnn_plan_set_tiles": ([vp, i32, i32], i32),
         "pecnn_plan_get_tiles": ([vp, P(i32), P(i32)], i32),
+        "pecnn_plan_set_pressure": ([vp, vp, vp], i32),
         "cloth_ms_step": ([vp, P(MsParams), vp, vp, i32, vp, vp, sz, vp], i32),
         "pecnn_theta_size": ([i32], i64),
         "pecnn_forward": ([vp, P(Model), vp, vp, vp, vp], i32),
@@ -88,7 +89,8 @@ def lib():
 
 def exported_symbols():
     return ["pecnn_plan_device_bytes", "pecnn_plan_create", "pecnn_plan_destroy", "pecnn_plan_nodes",
-            "pecnn_plan_set_tiles", "pecnn_plan_get_tiles", "cloth_ms_step", "pecnn_theta_size",
+            "pecnn_plan_set_tiles", "pecnn_plan_get_tiles", "pecnn_plan_set_pressure", "cloth_ms_step",
+            "pecnn_theta_size",
             "pecnn_forward", "pecnn_backward", "pecnn_rollout", "cloth_reduce_fp64", "pecnn_loss_mse",
             "pecnn_adam_step", "pecnn_gather_windows", "pecnn_workspace_bytes", "pecnn_autotune",
             "pecnn_status_string", "pecnn_last_error", "pecnn_version"]
@@ -153,7 +155,18 @@ class Plan:
 
     @classmethod
     def from_batch(cls, batch, device="cuda"):
-        return cls(batch.H, batch.W, batch.h, batch.mass, batch.a_ext, batch.pin, device)
+        plan = cls(batch.H, batch.W, batch.h, batch.mass, batch.a_ext, batch.pin, device)
+        pres = getattr(batch, "pressure", None)
+        if pres is not None and np.any(np.asarray(pres) != 0):
+            plan.set_pressure(pres)
+        return plan
+
+    def set_pressure(self, pressure):
+        """Per-instance uniform pressure of eq. (3), N/m^2 (pecnn_plan_set_pressure)."""
+        self._p = np.ascontiguousarray(pressure, np.float32).reshape(-1)
+        if self._p.size != self.n:
+            raise ValueError("need one pressure per instance")
+        check(lib().pecnn_plan_set_pressure(self.handle, self._p.ctypes.data, _stream()), "pecnn_plan_set_pressure")
 
     def close(self):
         if getattr(self, "handle", None) is not None and _lib is not None:

@@ -121,7 +121,8 @@ static void graph_cache_free(pecnn_plan* plan) {
 
 // ---------------------------------------------------------------- guard kernels
 // Every check: per instance, compare the largest structural stretch ratio and the energy gain
-// with the guard's bounds; a tripped instance falls back for good. Also counts fallen instances.
+// with the guard's bounds (no energy check where the energy scale is infinite: instances with a
+// pressure); a tripped instance falls back for good. Also counts fallen instances.
 // count[0] receives the number of fallen instances, count[1] keeps the index of the check.
 __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restrict__ now, double* __restrict__ e0,
                                                     const double* __restrict__ eref, pecnn_guard G, int init,
@@ -139,7 +140,8 @@ __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restr
       stats[4 * b + 2] = st;
       stats[4 * b + 3] = fallback[b] ? 0.0 : -1.0;
     } else if (fallback[b] == 0 &&
-               (!(st <= (double)G.stretch_max) || !((e - e0[b]) / eref[b] <= (double)G.energy_gain_max))) {
+               (!(st <= (double)G.stretch_max) ||
+                (isfinite(eref[b]) && !((e - e0[b]) / eref[b] <= (double)G.energy_gain_max)))) {
       fallback[b] = 1;
       stats[4 * b + 3] = step;
     }
@@ -286,7 +288,7 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
     hi[b].ax = d->a_ext[3 * b];
     hi[b].ay = d->a_ext[3 * b + 1];
     hi[b].az = d->a_ext[3 * b + 2];
-    hi[b].pad = 0;
+    hi[b].pres = 0.f;
     off += (int64_t)d->H[b] * d->W[b];
     if (d->H[b] * d->W[b] > max_hw) max_hw = d->H[b] * d->W[b];
   }
@@ -331,7 +333,8 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
   p->h = (float*)malloc(sizeof(float) * n);
   p->mass = (float*)malloc(sizeof(float) * n);
   p->a_ext = (float*)malloc(sizeof(float) * 3 * n);
-  if (!p->H || !p->W || !p->off || !p->h || !p->mass || !p->a_ext) {
+  p->pres = (float*)calloc(n, sizeof(float));
+  if (!p->H || !p->W || !p->off || !p->h || !p->mass || !p->a_ext || !p->pres) {
     pecnn_plan_destroy(p);
     set_error("out of host memory");
     return PECNN_E_INVALID;
@@ -373,7 +376,37 @@ int pecnn_plan_destroy(pecnn_plan* p) {
   free(p->h);
   free(p->mass);
   free(p->a_ext);
+  free(p->pres);
   free(p);
+  return PECNN_OK;
+}
+
+int pecnn_plan_set_pressure(pecnn_plan* p, const float* pressure, void* stream) {
+  if (check_plan(p)) return PECNN_E_INVALID;
+  if (!pressure) { set_error("null pressure"); return PECNN_E_INVALID; }
+  for (int b = 0; b < p->n; ++b)
+    if (!isfinite(pressure[b])) { set_error("instance %d: pressure must be finite", b); return PECNN_E_INVALID; }
+  // rebuild the instance records from the host copies and replace them in the plan memory
+  std::vector<InstDev> hi(p->n);
+  int any = 0;
+  for (int b = 0; b < p->n; ++b) {
+    hi[b].H = p->H[b];
+    hi[b].W = p->W[b];
+    hi[b].off = p->off[b];
+    hi[b].h = p->h[b];
+    hi[b].mass = p->mass[b];
+    hi[b].ax = p->a_ext[3 * b];
+    hi[b].ay = p->a_ext[3 * b + 1];
+    hi[b].az = p->a_ext[3 * b + 2];
+    hi[b].pres = pressure[b];
+    any |= pressure[b] != 0.f;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  PECNN_HIP(hipMemcpyAsync(p->d_inst, hi.data(), sizeof(InstDev) * p->n, hipMemcpyHostToDevice, st));
+  PECNN_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < p->n; ++b) p->pres[b] = pressure[b];
+  if (any != p->has_pressure) graph_cache_free(p);  // captured chunks hold the other kernel variants
+  p->has_pressure = any;
   return PECNN_OK;
 }
 
@@ -575,6 +608,8 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     for (int b = 0; b < p->n; ++b) {
       double e = (double)p->H[b] * p->W[b] * p->mass[b] * (gn > 0 ? gn : 1.0) * (p->W[b] > 1 ? p->W[b] - 1 : 1) * p->h[b];
       eref[b] = e > 0 ? e : 1.0;
+      // pressure does work on the cloth, so its energy may rise: the energy check is off there
+      if (p->pres[b] != 0.f) eref[b] = INFINITY;
     }
     PECNN_HIP(hipMemcpyAsync(w.eref, eref.data(), sizeof(double) * p->n, hipMemcpyHostToDevice, st));
     rc = reduce_launch(p, sim, s_cur, nullptr, w.now, w.part, st);

@@ -183,11 +183,12 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
 }
 
 // For node q: g_cur/g_prev += direct terms of eq. (5) + adjoint of the clamped, centre-differenced
-// im2col: a tap (c, o) of node p read S_c(clamp(p + o)) (and, for positions, -S_c(p)).
+// im2col: a tap (c, o) of node p read S_c(clamp(p + o)) (and, for positions, -S_c(p)); plus, with a
+// pressure, the adjoint of the eq. (3) term of q and of its four neighbours, which read x_q.
 __global__ __launch_bounds__(256) void bwd_gather_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
-    const uint8_t* __restrict__ pin, const float* __restrict__ g_next, int64_t N, float dt, int ch,
-    const float* __restrict__ fac, float* __restrict__ g_cur, float* __restrict__ g_prev) {
+    const uint8_t* __restrict__ pin, const float* __restrict__ s_cur, const float* __restrict__ g_next, int64_t N,
+    float dt, int ch, const float* __restrict__ fac, float* __restrict__ g_cur, float* __restrict__ g_prev) {
   int b;
   int local;
   if (!chunk_node(inst, prefix, chunk_inst, blockIdx.x, b, local)) return;
@@ -228,6 +229,37 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(
       accC[c] -= gus[fac_node(q, L.rows) + (c * 9 + o) * 32];
       accP[c] += gud[fac_node(q, L.rows) + (c * 9 + o) * 32];
     }
+  if (I.pres != 0.f) {
+    // the term c (x_j1 - x_P) x (x_j2 - x_P) of node P with adjoint l = dLoss/dv' (zero when P
+    // is pinned), c = dt p / m: d/dx_j1 = c (x_j2 - x_P) x l, d/dx_j2 = c l x (x_j1 - x_P),
+    // d/dx_P = minus both. Node q takes the parts where it is P, j1 or j2.
+    const int R[4][2] = {{0, 1}, {1, 0}, {0, -1}, {-1, 0}};  // right, down, left, up
+    const float c = dt * I.pres / I.mass;
+    for (int o = 0; o < 5; ++o) {
+      const int pi = qi + (o == 0 ? 0 : R[o - 1][0]), pj = qj + (o == 0 ? 0 : R[o - 1][1]);
+      if (pi < 0 || pi >= I.H || pj < 0 || pj >= I.W) continue;
+      const int64_t P = I.off + (int64_t)pi * I.W + pj;
+      const float l0 = fac[fac_node(P, L.rows) + (L.gdv + 0) * 32];
+      const float l1 = fac[fac_node(P, L.rows) + (L.gdv + 1) * 32];
+      const float l2 = fac[fac_node(P, L.rows) + (L.gdv + 2) * 32];
+      const float xp0 = s_cur[P], xp1 = s_cur[N + P], xp2 = s_cur[2 * N + P];
+      for (int k = 0; k < 4; ++k) {
+        const int i1 = pi + R[k][0], j1 = pj + R[k][1];
+        const int i2 = pi + R[(k + 1) & 3][0], j2 = pj + R[(k + 1) & 3][1];
+        if (i1 < 0 || i1 >= I.H || j1 < 0 || j1 >= I.W || i2 < 0 || i2 >= I.H || j2 < 0 || j2 >= I.W) continue;
+        const bool is1 = i1 == qi && j1 == qj, is2 = i2 == qi && j2 == qj;
+        if (o != 0 && !is1 && !is2) continue;
+        const int64_t q1 = I.off + (int64_t)i1 * I.W + j1, q2 = I.off + (int64_t)i2 * I.W + j2;
+        const float A0 = s_cur[q1] - xp0, A1 = s_cur[N + q1] - xp1, A2 = s_cur[2 * N + q1] - xp2;
+        const float B0 = s_cur[q2] - xp0, B1 = s_cur[N + q2] - xp1, B2 = s_cur[2 * N + q2] - xp2;
+        const float g10 = c * (B1 * l2 - B2 * l1), g11 = c * (B2 * l0 - B0 * l2), g12 = c * (B0 * l1 - B1 * l0);
+        const float g20 = c * (l1 * A2 - l2 * A1), g21 = c * (l2 * A0 - l0 * A2), g22 = c * (l0 * A1 - l1 * A0);
+        if (is1) { accC[0] += g10; accC[1] += g11; accC[2] += g12; }
+        if (is2) { accC[0] += g20; accC[1] += g21; accC[2] += g22; }
+        if (o == 0) { accC[0] -= g10 + g20; accC[1] -= g11 + g21; accC[2] -= g12 + g22; }
+      }
+    }
+  }
   // eq. (5): x' = x + dt v', v' = C(v + dv + dt a)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -449,8 +481,8 @@ int backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* s
   }
   PECNN_LAUNCH_CHECK("bwd_node_kernel");
   if (gc || gp) {
-    hipLaunchKernelGGL(bwd_gather_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, gn,
-                       plan->total, m->dt, m->ch, fac, gc, gp);
+    hipLaunchKernelGGL(bwd_gather_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, sc,
+                       gn, plan->total, m->dt, m->ch, fac, gc, gp);
     PECNN_LAUNCH_CHECK("bwd_gather_kernel");
   }
   const size_t lds = (size_t)(L.rows + 16) * (kWgSub + 4) * sizeof(float);

@@ -121,6 +121,21 @@ __global__ __launch_bounds__(256) void cnn_fwd_kernel(
         float nx = (vx + dv[0]) + __builtin_fmaf(dt, I.ax, bias0);
         float ny = (vy + dv[1]) + __builtin_fmaf(dt, I.ay, bias1);
         float nz = (vz + dv[2]) + __builtin_fmaf(dt, I.az, bias2);
+        if (I.pres != 0.f) {  // eq. (3) at S^k, a known external force (uniform over the workgroup)
+          const int nb[4] = {1, HX, -1, -HX};  // right, down, left, up
+          float d[4][3];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d[q][c] = tS[c * PL + base + nb[q]] - tS[c * PL + base];
+          const bool has[4] = {j + 1 < I.W, i + 1 < I.H, j > 0, i > 0};
+          float p0, p1, p2;
+          pressure_pairs(d, has, p0, p1, p2);
+          const float cp = dt * I.pres / I.mass;
+          nx = __builtin_fmaf(cp, p0, nx);
+          ny = __builtin_fmaf(cp, p1, ny);
+          nz = __builtin_fmaf(cp, p2, nz);
+        }
         if (pin[p]) nx = ny = nz = 0.f;
         s_next[3 * N + p] = nx;
         s_next[4 * N + p] = ny;

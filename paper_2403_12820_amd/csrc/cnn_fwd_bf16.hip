@@ -21,7 +21,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // WPE: waves per SIMD the register allocation is held to (3 fits the tiles up to 256 nodes).
 // VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
 // so the halo rows load as 16-byte pieces; otherwise as single floats.
-template <int CH, int TX, int TY, bool A1, int WPE, bool VEC>
+// PRES: some instance of the batch has a pressure (eq. 3), added as a known external force.
+template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool PRES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void cnn_fwd_bf16_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_prev, const float* __restrict__ s_cur,
@@ -332,6 +333,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             float nx = (tS[3 * PLN + cell] + e0) + cx;
             float ny = (tS[4 * PLN + cell] + e1) + cy;
             float nz = (tS[5 * PLN + cell] + e2) + cz;
+            if constexpr (PRES) {
+              if (Ic.pres != 0.f) {  // eq. (3) at S^k, uniform over the workgroup
+                const int nb[4] = {1, RS, -1, -RS};  // right, down, left, up
+                float d[4][3];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) d[q][c] = tS[c * PLN + cell + nb[q]] - tS[c * PLN + cell];
+                const bool has[4] = {j + 1 < Ic.W, i + 1 < Ic.H, j > 0, i > 0};
+                float p0, p1, p2;
+                pressure_pairs(d, has, p0, p1, p2);
+                const float cp = dt * Ic.pres / Ic.mass;
+                nx = __builtin_fmaf(cp, p0, nx);
+                ny = __builtin_fmaf(cp, p1, ny);
+                nz = __builtin_fmaf(cp, p2, nz);
+              }
+            }
             if (tP[sy * TX + sx]) nx = ny = nz = 0.f;
             gst(s_next, 3 * N32 + p, nx);
             gst(s_next, 4 * N32 + p, ny);
@@ -349,14 +367,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-template <int CH, int TX, int TY, bool A1, int WPE, bool VEC>
+template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool PRES>
 static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const float* sc, float* sn,
                         const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
   const int n_tiles = plan->n_tiles[slot];
   static int per_cu = 0;  // resident workgroups per CU of this instantiation
   if (per_cu == 0) {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC, PRES>, 256, 0) !=
+            hipSuccess ||
         v < 1)
       v = 2;
     per_cu = v;
@@ -365,20 +384,20 @@ static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const
   const int need = ((n_tiles + 7) / 8) * 8;
   if (need < grid) grid = need;
   if (grid < 8) grid = 8;
-  hipLaunchKernelGGL((cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC>), dim3(grid), dim3(256), 0, st, plan->d_inst,
+  hipLaunchKernelGGL((cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC, PRES>), dim3(grid), dim3(256), 0, st, plan->d_inst,
                      plan->d_prefix[slot], plan->n, n_tiles, plan->pin, sp, sc, sn, plan->total, theta, dt, alpha,
                      skip);
 }
 
-template <int CH, bool A1, bool VEC>
+template <int CH, bool A1, bool VEC, bool PRES>
 static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                       const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
   const int slot = cnn_cfg_slot(cfg);
   switch (cfg) {
-    case 0: launch_bf16<CH, 64, 4, A1, 3, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 1: launch_bf16<CH, 32, 8, A1, 3, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 2: launch_bf16<CH, 16, 16, A1, 3, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 3: launch_bf16<CH, 64, 8, A1, 2, VEC>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 0: launch_bf16<CH, 64, 4, A1, 3, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 1: launch_bf16<CH, 32, 8, A1, 3, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 2: launch_bf16<CH, 16, 16, A1, 3, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 3: launch_bf16<CH, 64, 8, A1, 2, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
     default: return PECNN_E_INVALID;
   }
   return PECNN_OK;
@@ -387,8 +406,11 @@ static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const fl
 template <int CH, bool A1>
 static int bf16_cfg(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                     const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
-  return plan->vec4 ? bf16_cfg_v<CH, A1, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)
-                    : bf16_cfg_v<CH, A1, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+  if (plan->has_pressure)
+    return plan->vec4 ? bf16_cfg_v<CH, A1, true, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)
+                      : bf16_cfg_v<CH, A1, false, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+  return plan->vec4 ? bf16_cfg_v<CH, A1, true, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)
+                    : bf16_cfg_v<CH, A1, false, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
 }
 
 int cnn_forward_bf16_launch(const pecnn_plan* plan, int cfg, const pecnn_model* m, const float* sp,

@@ -15,7 +15,7 @@ struct InstDev {
   int64_t off;     // first node of the instance in the batch planes
   float h, mass;   // rest spacing, node mass
   float ax, ay, az;  // constant external (wind) acceleration
-  int32_t pad;
+  float pres;        // uniform pressure of eq. (3), N/m^2 (0: none)
 };
 static_assert(sizeof(InstDev) == 40, "InstDev layout");
 
@@ -110,6 +110,28 @@ __device__ __forceinline__ void gst(T* __restrict__ base, unsigned idx, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(float)) = v;
 }
 
+// Eq. (3) at one node: the four nearest neighbours taken round the node in the order right,
+// down, left, up; each consecutive pair (j1, j2) whose two nodes are on the grid adds
+// (x_j1 - x) x (x_j2 - x). On the flat rest grid (x along columns, y along rows) every pair
+// gives +h^2 along z. d[k] = x_k - x for k = right, down, left, up; has[k] says whether the
+// neighbour is on the grid (a missing neighbour's d may hold anything finite).
+__device__ __forceinline__ void pressure_pairs(const float (&d)[4][3], const bool (&has)[4], float& s0, float& s1,
+                                               float& s2) {
+  s0 = s1 = s2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float* a = d[k];
+    const float* b = d[(k + 1) & 3];
+    const float c0 = __builtin_fmaf(a[1], b[2], -(a[2] * b[1]));
+    const float c1 = __builtin_fmaf(a[2], b[0], -(a[0] * b[2]));
+    const float c2 = __builtin_fmaf(a[0], b[1], -(a[1] * b[0]));
+    const bool on = has[k] && has[(k + 1) & 3];
+    s0 += on ? c0 : 0.f;
+    s1 += on ? c1 : 0.f;
+    s2 += on ? c2 : 0.f;
+  }
+}
+
 struct MsParamsDev {
   float k[3];     // spring constants per family
   float mu, drag;
@@ -138,6 +160,8 @@ struct pecnn_plan {
   int32_t cnn_cfg;
   int32_t max_hw;                       // largest H*W of an instance
   int32_t vec4;                         // every row of every plane starts 16-byte aligned
+  float* pres;                          // host copy of the per-instance pressure (eq. 3)
+  int32_t has_pressure;                 // some instance has a non-zero pressure
   void* graph_cache;                    // rollout graph cache (host object)
 };
 

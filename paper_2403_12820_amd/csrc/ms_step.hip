@@ -20,7 +20,8 @@ __device__ constexpr Spring kSprings[12] = {
 
 // VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
 // so the tile rows load as 16-byte pieces; otherwise as single floats.
-template <int TX, int TY, int RY, bool VEC>
+// PRES: some instance of the batch has a pressure (eq. 3); the others skip it uniformly.
+template <int TX, int TY, int RY, bool VEC, bool PRES>
 __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_in, float* __restrict__ s_out,
@@ -199,6 +200,24 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
               f1 = __builtin_fmaf(cf, d1, f1);
               f2 = __builtin_fmaf(cf, d2, f2);
             }
+            if constexpr (PRES) {
+              if (Ic.pres != 0.f) {  // eq. (3), uniform over the workgroup
+                const int nb[4] = {1, RS, -1, -RS};  // right, down, left, up
+                float d[4][3];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  d[k][0] = lds[e + nb[k]] - x0;
+                  d[k][1] = lds[PLN + e + nb[k]] - x1;
+                  d[k][2] = lds[2 * PLN + e + nb[k]] - x2;
+                }
+                const bool has[4] = {j + 1 < Ic.W, i + 1 < Ic.H, j > 0, i > 0};
+                float s0, s1, s2;
+                pressure_pairs(d, has, s0, s1, s2);
+                f0 = __builtin_fmaf(Ic.pres, s0, f0);
+                f1 = __builtin_fmaf(Ic.pres, s1, f1);
+                f2 = __builtin_fmaf(Ic.pres, s2, f2);
+              }
+            }
             // eq. (5): semi-implicit Euler
             n0 = __builtin_fmaf(sc, f0, v0);
             n1 = __builtin_fmaf(sc, f1, v1);
@@ -233,14 +252,17 @@ static void launch_ms(const pecnn_plan* plan, int slot, const MsParamsDev& P, co
                       float* out, const uint8_t* active, hipStream_t st) {
   const int n_tiles = plan->n_tiles[slot];
   const int grid = grid_for(n_tiles, 8);
-  if (plan->vec4)
-    hipLaunchKernelGGL((ms_step_kernel<TX, TY, RY, true>), dim3(grid), dim3(TX * (TY / RY)), 0, st,
-                       plan->d_inst, plan->d_prefix[slot], plan->n, n_tiles, plan->pin, in, out,
-                       plan->total, P, active);
-  else
-    hipLaunchKernelGGL((ms_step_kernel<TX, TY, RY, false>), dim3(grid), dim3(TX * (TY / RY)), 0, st,
-                       plan->d_inst, plan->d_prefix[slot], plan->n, n_tiles, plan->pin, in, out,
-                       plan->total, P, active);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(TX * (TY / RY)), 0, st, plan->d_inst, plan->d_prefix[slot], plan->n,
+                       n_tiles, plan->pin, in, out, plan->total, P, active);
+  };
+  if (plan->has_pressure) {
+    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, true>);
+    else go(ms_step_kernel<TX, TY, RY, false, true>);
+  } else {
+    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, false>);
+    else go(ms_step_kernel<TX, TY, RY, false, false>);
+  }
 }
 
 MsParamsDev ms_params_dev(const cloth_ms_params* p) {

@@ -123,6 +123,7 @@ class Scene:
     pin: np.ndarray             # uint8 [H*W]
     state: np.ndarray           # float32 [6, H*W]
     pin_kind: str = ""
+    pressure: float = 0.0       # uniform pressure of eq. (3), N/m^2 (float32 value)
 
     @property
     def n(self) -> int:
@@ -131,7 +132,7 @@ class Scene:
 
 def make_scene(H: int, W: int, pin_kind: str = "two_top_corners", wind=(0.0, 0.0, 0.0),
                noise_sigma: float = 1e-3, seed: int = 0, mat: Material | None = None,
-               v0=None) -> Scene:
+               v0=None, pressure: float = 0.0) -> Scene:
     """Flat cloth at rest plus z-noise N(0, sigma^2) on unpinned nodes (one draw per node, p = i*W + j)."""
     mat = mat or Material()
     X = flat_grid(H, W, mat.h)
@@ -144,7 +145,7 @@ def make_scene(H: int, W: int, pin_kind: str = "two_top_corners", wind=(0.0, 0.0
     if v0 is not None:
         s[3:] = np.asarray(v0, np.float32).reshape(3, -1)
     return Scene(H, W, float(np.float32(mat.h)), float(np.float32(mat.mass)),
-                 np.asarray(wind, np.float64), pin, s, pin_kind)
+                 np.asarray(wind, np.float64), pin, s, pin_kind, float(np.float32(pressure)))
 
 
 def random_scene_params(n: int, seed: int):
@@ -187,6 +188,7 @@ class Batch:
     pin: np.ndarray             # uint8 [N_total]
     state: np.ndarray           # float32 [6, N_total]
     node_off: np.ndarray = field(default=None)  # int64 [n+1]
+    pressure: np.ndarray = field(default=None)  # float32 [n], eq. (3)
 
     @property
     def n(self) -> int:
@@ -212,7 +214,8 @@ def make_batch(scenes) -> Batch:
                  np.array([s.a_ext for s in scenes], np.float32).reshape(-1, 3),
                  np.concatenate([s.pin for s in scenes]).astype(np.uint8),
                  np.concatenate([s.state for s in scenes], axis=1).astype(np.float32),
-                 off)
+                 off,
+                 np.array([getattr(s, "pressure", 0.0) for s in scenes], np.float32))
 
 
 # --------------------------------------------------------------------------- weights
