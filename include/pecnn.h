@@ -119,15 +119,28 @@ enum { PECNN_FP32 = 0, PECNN_BF16 = 1 };
    b_L[3] (pecnn_theta_size(Ch) floats). precision PECNN_BF16 rounds the operands of the
    convolution, of A and B and of the three heads to bfloat16 (round to nearest even) with FP32
    accumulation; PECNN_FP32 keeps every operand in FP32. State and integration stay FP32. */
+enum { PECNN_CELL_CONV = 0, PECNN_CELL_PAIR = 1 };
+
+/* cell PECNN_CELL_CONV (default): the channel-mixing convolution cell described above.
+   cell PECNN_CELL_PAIR: section 3.2's own cell read literally, Ch = 12 and FP32 only. Channel c
+   belongs to neighbour j = i + o_c of the 13-point stencil (o_c in the spring order (0,1),
+   (0,-1), (1,0), (-1,0), (1,1), (1,-1), (-1,1), (-1,-1), (0,2), (0,-2), (2,0), (-2,0)); its
+   filter is predetermined (+s_c at j, -s_c at the centre, zero elsewhere) and acts alike on each
+   axis (eq. 6):  phi_c = s_c (x_j - x_i),  xi_c = s_c (v_j - v_i)  (zero when j is off the grid).
+   Eq. (7) axis by axis: dv = sum_c [wL_c phi_c + wN_c sigma(phi_c) + wD_c xi_c sigma(phi_c)] + b_L.
+   theta: s[12] | wL[12] | wN[12] | wD[12] | b_L[3] (51 floats). It reads S^k only (S^{k-1} is
+   ignored) and runs on the mass-spring step's tiles (configuration ms_cfg). */
 typedef struct {
   int32_t ch;
   int32_t precision;
   float dt;          /* time step of one network step (eq. 5 inside the frame), > 0 */
   float isru_alpha;  /* ISRU sigma(z) = z / sqrt(1 + alpha z^2), alpha > 0 */
   const float* theta;
+  int32_t cell;      /* PECNN_CELL_CONV or PECNN_CELL_PAIR */
 } pecnn_model;
 
-int64_t pecnn_theta_size(int32_t ch);
+int64_t pecnn_theta_size(int32_t ch);                       /* the convolution cell */
+int64_t pecnn_cell_theta_size(int32_t cell, int32_t ch);    /* either cell; -1 if unsupported */
 
 /* One network frame (Fig. 2): per node p,
      U(S)[c][o] = S_c(clamp(p+o)) - [c < 3] S_c(p)    (o in {-1,0,1}^2, clamp-to-edge)

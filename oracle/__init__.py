@@ -12,6 +12,8 @@ Paper passages followed (section / equation):
   cnn_forward                - section 3.2, eqs. (6), (7), then (5) (Fig. 2), with wind and the
                                pressure of eq. (3) as known external forces
   cnn_backward               - section 3.2.1, reverse mode of the above
+  pair_forward, pair_backward - section 3.2 read literally: twelve frozen neighbour-difference
+                               channels shared by the axes, eqs. (6), (7), then (5)
   loss_mse                   - eq. (8), data term
   adam                       - Table 1 (optimizer Adam)
   energy, max_stretch, rms   - diagnostics of the rollout (no paper formula)
@@ -61,6 +63,10 @@ def _load():
         _lib.or_theta_size.restype = l
         _lib.or_cnn_forward.argtypes = [i, i, i, d, d, p, d, p, p, p, p, p, i, p]
         _lib.or_cnn_backward.argtypes = [i, i, i, d, d, d, p, p, p, p, p, p, p, p]
+        _lib.or_pair_theta_size.argtypes = []
+        _lib.or_pair_theta_size.restype = l
+        _lib.or_pair_forward.argtypes = [i, i, d, d, p, d, p, p, p, p, p]
+        _lib.or_pair_backward.argtypes = [i, i, d, d, d, p, p, p, p, p, p]
         _lib.or_loss_mse.argtypes = [l, p, l, d, d, d, p, p, p]
         _lib.or_loss_mse.restype = d
         _lib.or_adam.argtypes = [l, d, d, d, d, i, p, p, p, p]
@@ -159,6 +165,29 @@ def cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev, s_cur, g_next, pm=0.0)
     return gc, gp, gt
 
 
+def pair_theta_size() -> int:
+    return int(_load().or_pair_theta_size())
+
+
+def pair_forward(H, W, alpha, dt, a_ext, pin, theta, s_cur, pm=0.0):
+    """The paper's pair cell, one frame: returns (s_next [6, n], dv [3, n])."""
+    sc = _f64(s_cur).reshape(6, H * W)
+    th, a, pn = _f64(theta), _f64(a_ext), _u8(pin)
+    assert th.size == pair_theta_size()
+    out, dv = np.empty((6, H * W)), np.empty((3, H * W))
+    _load().or_pair_forward(H, W, alpha, dt, _ptr(a), float(pm), _ptr(pn), _ptr(th), _ptr(sc), _ptr(out), _ptr(dv))
+    return out, dv
+
+
+def pair_backward(H, W, alpha, dt, pin, theta, s_cur, g_next, pm=0.0):
+    """Returns (g_cur, g_theta) for g_next = dLoss/dS^{k+1}."""
+    sc, gn = _f64(s_cur).reshape(6, H * W), _f64(g_next).reshape(6, H * W)
+    th, pn = _f64(theta), _u8(pin)
+    gc, gt = np.zeros((6, H * W)), np.zeros(th.size)
+    _load().or_pair_backward(H, W, alpha, dt, float(pm), _ptr(pn), _ptr(th), _ptr(sc), _ptr(gn), _ptr(gc), _ptr(gt))
+    return gc, gt
+
+
 def loss_mse(pin, n_free, sx, sv, w, s_hat, s_true, want_grad=True):
     sh, st = _f64(s_hat).reshape(6, -1), _f64(s_true).reshape(6, -1)
     n = sh.shape[1]
@@ -221,3 +250,26 @@ def batch_cnn_backward(batch, ch, alpha, dt, theta, s_prev, s_cur, g_next):
         gp[:, sl] += p
         gt += t
     return gc, gp, gt
+
+
+def batch_pair_forward(batch, alpha, dt, theta, s_cur):
+    s_cur = _f64(s_cur)
+    out = np.empty_like(s_cur)
+    dv = np.empty((3, s_cur.shape[1]))
+    for b in range(batch.n):
+        H, W, h, m, a, pin = _inst(batch, b)
+        sl = batch.instance(b)
+        out[:, sl], dv[:, sl] = pair_forward(H, W, alpha, dt, a, pin, theta, s_cur[:, sl], _pressure(batch, b) / m)
+    return out, dv
+
+
+def batch_pair_backward(batch, alpha, dt, theta, s_cur, g_next):
+    gc = np.zeros((6, s_cur.shape[1]))
+    gt = np.zeros(np.asarray(theta).size)
+    for b in range(batch.n):
+        H, W, h, m, a, pin = _inst(batch, b)
+        sl = batch.instance(b)
+        c, t = pair_backward(H, W, alpha, dt, pin, theta, s_cur[:, sl], g_next[:, sl], _pressure(batch, b) / m)
+        gc[:, sl] += c
+        gt += t
+    return gc, gt

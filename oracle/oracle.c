@@ -18,6 +18,9 @@
  *     pressure of eq. (3) added as known external forces;
  *   - its exact reverse mode (section 3.2.1: gradient backpropagation), the
  *     data term of the eq. (8) loss and Adam (Table 1);
+ *   - section 3.2's own cell read literally ("pair cell": twelve frozen
+ *     neighbour-difference channels shared by the three axes, per-channel branch
+ *     weights, eqs. 6 and 7) with its reverse mode;
  *   - FP64 diagnostics: position RMS error, energy, stretch ratio.
  * Readings of passages the paper leaves open are listed in the design notes.
  *
@@ -373,6 +376,36 @@ void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double 
     free(dS);
 }
 
+/* Adjoint of c (x_j1 - x) x (x_j2 - x) summed over the pairs of node (i, j) (eq. 3), for the
+   adjoint gdv of the velocity it is added to: with A = x_j1 - x, B = x_j2 - x,
+   d/dx_j1 = c B x gdv, d/dx_j2 = c gdv x A, d/dx = minus both. Accumulates into g (positions). */
+static void or_pressure_adjoint(int H, int W, const double *s, int i, int j, double c, const double *gdv,
+                                double *g)
+{
+    static const int R[4][2] = {{0, 1}, {1, 0}, {0, -1}, {-1, 0}};
+    const long n = (long)H * W, p = (long)i * W + j;
+    for (int k = 0; k < 4; ++k) {
+        const int i1 = i + R[k][0], j1 = j + R[k][1];
+        const int i2 = i + R[(k + 1) % 4][0], j2 = j + R[(k + 1) % 4][1];
+        if (i1 < 0 || i1 >= H || j1 < 0 || j1 >= W || i2 < 0 || i2 >= H || j2 < 0 || j2 >= W) continue;
+        const long q1 = (long)i1 * W + j1, q2 = (long)i2 * W + j2;
+        double A[3], B[3];
+        for (int a = 0; a < 3; ++a) {
+            A[a] = s[a * n + q1] - s[a * n + p];
+            B[a] = s[a * n + q2] - s[a * n + p];
+        }
+        const double g1[3] = {c * (B[1] * gdv[2] - B[2] * gdv[1]), c * (B[2] * gdv[0] - B[0] * gdv[2]),
+                              c * (B[0] * gdv[1] - B[1] * gdv[0])};
+        const double g2[3] = {c * (gdv[1] * A[2] - gdv[2] * A[1]), c * (gdv[2] * A[0] - gdv[0] * A[2]),
+                              c * (gdv[0] * A[1] - gdv[1] * A[0])};
+        for (int a = 0; a < 3; ++a) {
+            g[a * n + q1] += g1[a];
+            g[a * n + q2] += g2[a];
+            g[a * n + p] -= g1[a] + g2[a];
+        }
+    }
+}
+
 /* Reverse mode of or_cnn_forward (emu = 0). Given g_next = dLoss/dS^{k+1}, accumulate
    dLoss/dS^k into g_cur, dLoss/dS^{k-1} into g_prev and dLoss/dtheta into g_theta. */
 void or_cnn_backward(int H, int W, int ch, double alpha, double dt, double pm, const uint8_t *pin,
@@ -395,32 +428,7 @@ void or_cnn_backward(int H, int W, int ch, double alpha, double dt, double pm, c
                 gdv[a] = pin[p] ? 0.0 : gvt;
                 g_cur[(3 + a) * n + p] += gdv[a];
             }
-            /* pressure term c (x_j1 - x) x (x_j2 - x), c = dt pm: with A = x_j1 - x, B = x_j2 - x and
-               the adjoint gdv, d/dx_j1 = c B x gdv, d/dx_j2 = c gdv x A, d/dx = minus both */
-            if (pm != 0.0) {
-                static const int R[4][2] = {{0, 1}, {1, 0}, {0, -1}, {-1, 0}};
-                const double c = dt * pm;
-                for (int k = 0; k < 4; ++k) {
-                    const int i1 = i + R[k][0], j1 = j + R[k][1];
-                    const int i2 = i + R[(k + 1) % 4][0], j2 = j + R[(k + 1) % 4][1];
-                    if (i1 < 0 || i1 >= H || j1 < 0 || j1 >= W || i2 < 0 || i2 >= H || j2 < 0 || j2 >= W) continue;
-                    const long q1 = (long)i1 * W + j1, q2 = (long)i2 * W + j2;
-                    double A[3], B[3];
-                    for (int a = 0; a < 3; ++a) {
-                        A[a] = s_cur[a * n + q1] - s_cur[a * n + p];
-                        B[a] = s_cur[a * n + q2] - s_cur[a * n + p];
-                    }
-                    const double g1[3] = {c * (B[1] * gdv[2] - B[2] * gdv[1]), c * (B[2] * gdv[0] - B[0] * gdv[2]),
-                                          c * (B[0] * gdv[1] - B[1] * gdv[0])};
-                    const double g2[3] = {c * (gdv[1] * A[2] - gdv[2] * A[1]), c * (gdv[2] * A[0] - gdv[0] * A[2]),
-                                          c * (gdv[0] * A[1] - gdv[1] * A[0])};
-                    for (int a = 0; a < 3; ++a) {
-                        g_cur[a * n + q1] += g1[a];
-                        g_cur[a * n + q2] += g2[a];
-                        g_cur[a * n + p] -= g1[a] + g2[a];
-                    }
-                }
-            }
+            if (pm != 0.0) or_pressure_adjoint(H, W, s_cur, i, j, dt * pm, gdv, g_cur);
             /* eq. (7) heads */
             for (int c = 0; c < ch; ++c) { gphi[c] = 0.0; gnn[c] = 0.0; gdd[c] = 0.0; }
             for (int r = 0; r < 3; ++r) {
@@ -474,6 +482,103 @@ void or_cnn_backward(int H, int W, int ch, double alpha, double dt, double pm, c
         }
     free(o);
     free(dS);
+}
+
+/* ------------------------------------------------------------------ the paper's own cell */
+
+/* Section 3.2 read literally ("pair cell"). Twelve channels, one per neighbour of the 13-point
+   stencil, in the order of the springs above. The filter of channel c is predetermined: +s_c at
+   its neighbour j, -s_c at the centre, zero (frozen) elsewhere, and the same 2-D filter acts on
+   each axis. Eq. (6) applies it to x^k and to v^k:
+     phi_c = s_c (x_j - x_i),  xi_c = s_c (v_j - v_i)   (3-vectors; zero when j is off the grid).
+   Eq. (7), axis by axis, summed over the channels, bias once:
+     dv = sum_c [ wL_c phi_c + wN_c sigma(phi_c) + wD_c xi_c * sigma(phi_c) ] + b_L.
+   Then eq. (5) with pins, wind and pressure as for the other cell.
+   theta: s[12] | wL[12] | wN[12] | wD[12] | bL[3]. */
+enum { OR_PS = 0, OR_PWL = 12, OR_PWN = 24, OR_PWD = 36, OR_PBL = 48, OR_PTOTAL = 51 };
+long or_pair_theta_size(void) { return OR_PTOTAL; }
+
+static void or_pair_node(int H, int W, double alpha, const double *th, const double *s, int i, int j,
+                         double *dv)
+{
+    const long n = (long)H * W, p = (long)i * W + j;
+    for (int a = 0; a < 3; ++a) dv[a] = th[OR_PBL + a];
+    for (int c = 0; c < 12; ++c) {
+        const int ii = i + OR_NB[c][0], jj = j + OR_NB[c][1];
+        if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
+        const long q = (long)ii * W + jj;
+        for (int a = 0; a < 3; ++a) {
+            const double phi = th[OR_PS + c] * (s[a * n + q] - s[a * n + p]);
+            const double xi = th[OR_PS + c] * (s[(3 + a) * n + q] - s[(3 + a) * n + p]);
+            const double sg = or_isru(phi, alpha);
+            dv[a] += th[OR_PWL + c] * phi + th[OR_PWN + c] * sg + th[OR_PWD + c] * xi * sg;
+        }
+    }
+}
+
+/* One frame with the pair cell: v' = C(v + dv + dt a_ext + dt pm f_p(x)), x' = x + dt v'. */
+void or_pair_forward(int H, int W, double alpha, double dt, const double *a_ext, double pm,
+                     const uint8_t *pin, const double *theta, const double *s_cur, double *s_next,
+                     double *dv_out)
+{
+    const long n = (long)H * W;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const long p = (long)i * W + j;
+            double dv[3], fp[3] = {0.0, 0.0, 0.0};
+            or_pair_node(H, W, alpha, theta, s_cur, i, j, dv);
+            if (pm != 0.0) or_pressure(H, W, s_cur, i, j, dt * pm, fp);
+            for (int a = 0; a < 3; ++a) {
+                if (dv_out) dv_out[a * n + p] = dv[a];
+                const double v = pin[p] ? 0.0 : s_cur[(3 + a) * n + p] + dv[a] + dt * a_ext[a] + fp[a];
+                s_next[(3 + a) * n + p] = v;
+                s_next[a * n + p] = s_cur[a * n + p] + dt * v;
+            }
+        }
+}
+
+/* Reverse mode of or_pair_forward: g_next = dLoss/dS^{k+1} gives dLoss/dS^k (into g_cur) and
+   dLoss/dtheta (into g_theta). */
+void or_pair_backward(int H, int W, double alpha, double dt, double pm, const uint8_t *pin,
+                      const double *theta, const double *s_cur, const double *g_next, double *g_cur,
+                      double *g_theta)
+{
+    const long n = (long)H * W;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const long p = (long)i * W + j;
+            double gdv[3];
+            for (int a = 0; a < 3; ++a) {
+                const double gvt = g_next[(3 + a) * n + p] + dt * g_next[a * n + p];
+                g_cur[a * n + p] += g_next[a * n + p];
+                gdv[a] = pin[p] ? 0.0 : gvt;
+                g_cur[(3 + a) * n + p] += gdv[a];
+                g_theta[OR_PBL + a] += gdv[a];
+            }
+            if (pm != 0.0) or_pressure_adjoint(H, W, s_cur, i, j, dt * pm, gdv, g_cur);
+            for (int c = 0; c < 12; ++c) {
+                const int ii = i + OR_NB[c][0], jj = j + OR_NB[c][1];
+                if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
+                const long q = (long)ii * W + jj;
+                const double sc = theta[OR_PS + c];
+                for (int a = 0; a < 3; ++a) {
+                    const double d = s_cur[a * n + q] - s_cur[a * n + p];
+                    const double e = s_cur[(3 + a) * n + q] - s_cur[(3 + a) * n + p];
+                    const double phi = sc * d, xi = sc * e;
+                    const double sg = or_isru(phi, alpha), sgd = or_isru_d(phi, alpha);
+                    g_theta[OR_PWL + c] += gdv[a] * phi;
+                    g_theta[OR_PWN + c] += gdv[a] * sg;
+                    g_theta[OR_PWD + c] += gdv[a] * xi * sg;
+                    const double gphi = gdv[a] * (theta[OR_PWL + c] + (theta[OR_PWN + c] + theta[OR_PWD + c] * xi) * sgd);
+                    const double gxi = gdv[a] * theta[OR_PWD + c] * sg;
+                    g_theta[OR_PS + c] += gphi * d + gxi * e;
+                    g_cur[a * n + q] += sc * gphi;
+                    g_cur[a * n + p] -= sc * gphi;
+                    g_cur[(3 + a) * n + q] += sc * gxi;
+                    g_cur[(3 + a) * n + p] -= sc * gxi;
+                }
+            }
+        }
 }
 
 /* ------------------------------------------------------------------ loss and Adam */

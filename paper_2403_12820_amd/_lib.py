@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libpecnn.so")
 
 PECNN_FP32, PECNN_BF16 = 0, 1
+CELL_CONV, CELL_PAIR = 0, 1
 WS_MS_STEP, WS_BACKWARD, WS_ROLLOUT, WS_REDUCE = 0, 1, 2, 3
 N_MS_CFG, N_CNN_CFG = 5, 4
 
@@ -35,7 +36,7 @@ class MsParams(C.Structure):
 
 class Model(C.Structure):
     _fields_ = [("ch", C.c_int32), ("precision", C.c_int32), ("dt", C.c_float), ("isru_alpha", C.c_float),
-                ("theta", C.c_void_p)]
+                ("theta", C.c_void_p), ("cell", C.c_int32)]
 
 
 class Guard(C.Structure):
@@ -66,6 +67,7 @@ def lib():
         "pecnn_plan_set_pressure": ([vp, vp, vp], i32),
         "cloth_ms_step": ([vp, P(MsParams), vp, vp, i32, vp, vp, sz, vp], i32),
         "pecnn_theta_size": ([i32], i64),
+        "pecnn_cell_theta_size": ([i32, i32], i64),
         "pecnn_forward": ([vp, P(Model), vp, vp, vp, vp], i32),
         "pecnn_backward": ([vp, P(Model), vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "pecnn_rollout": ([vp, P(Model), P(MsParams), P(Guard), vp, vp, i32, vp, vp, vp, sz, vp], i32),
@@ -90,7 +92,7 @@ def lib():
 def exported_symbols():
     return ["pecnn_plan_device_bytes", "pecnn_plan_create", "pecnn_plan_destroy", "pecnn_plan_nodes",
             "pecnn_plan_set_tiles", "pecnn_plan_get_tiles", "pecnn_plan_set_pressure", "cloth_ms_step",
-            "pecnn_theta_size",
+            "pecnn_theta_size", "pecnn_cell_theta_size",
             "pecnn_forward", "pecnn_backward", "pecnn_rollout", "cloth_reduce_fp64", "pecnn_loss_mse",
             "pecnn_adam_step", "pecnn_gather_windows", "pecnn_workspace_bytes", "pecnn_autotune",
             "pecnn_status_string", "pecnn_last_error", "pecnn_version"]
@@ -195,9 +197,9 @@ class Plan:
         return torch.empty(max(nb.value, 1), dtype=torch.uint8, device=self.mem.device)
 
 
-def make_model(theta, ch, precision=PECNN_FP32, dt=5e-3, alpha=1.0) -> Model:
+def make_model(theta, ch, precision=PECNN_FP32, dt=5e-3, alpha=1.0, cell=CELL_CONV) -> Model:
     m = Model()
-    m.ch, m.precision, m.dt, m.isru_alpha = ch, precision, dt, alpha
+    m.ch, m.precision, m.dt, m.isru_alpha, m.cell = ch, precision, dt, alpha, cell
     m.theta = theta.data_ptr()
     m._theta_ref = theta  # keep the tensor alive
     return m

@@ -21,6 +21,9 @@ int ms_step_run(const pecnn_plan*, int cfg, const MsParamsDev&, const float*, fl
 int cnn_forward_launch(const pecnn_plan*, int cfg, const pecnn_model*, const float*, const float*, float*,
                        const int32_t*, hipStream_t);
 size_t backward_ws_bytes(const pecnn_plan*, int ch);
+size_t pair_backward_ws_bytes(const pecnn_plan*);
+int pair_backward_launch(const pecnn_plan*, const pecnn_model*, const float*, const float*, float*, float*, void*,
+                         hipStream_t);
 int backward_launch(const pecnn_plan*, const pecnn_model*, const float*, const float*, const float*, float*,
                     float*, float*, void*, hipStream_t);
 size_t reduce_ws_bytes(const pecnn_plan*);
@@ -75,7 +78,15 @@ static int check_ms_params(const cloth_ms_params* p) {
 
 static int check_model(const pecnn_model* m) {
   if (!m || !m->theta) { set_error("null model or theta"); return PECNN_E_INVALID; }
-  if (m->ch != 16 && m->ch != 32) { set_error("channel count %d unsupported (16 or 32)", m->ch); return PECNN_E_UNSUPPORTED; }
+  if (m->cell == PECNN_CELL_PAIR) {
+    if (m->ch != 12 || m->precision != PECNN_FP32) {
+      set_error("the pair cell has 12 channels and FP32 operands");
+      return PECNN_E_UNSUPPORTED;
+    }
+  } else if (m->cell != PECNN_CELL_CONV) {
+    set_error("cell %d unsupported", m->cell);
+    return PECNN_E_UNSUPPORTED;
+  } else if (m->ch != 16 && m->ch != 32) { set_error("channel count %d unsupported (16 or 32)", m->ch); return PECNN_E_UNSUPPORTED; }
   if (m->precision != PECNN_FP32 && m->precision != PECNN_BF16) { set_error("precision %d unsupported", m->precision); return PECNN_E_UNSUPPORTED; }
   if (!finite_pos(m->dt) || !finite_pos(m->isru_alpha)) { set_error("model dt and isru_alpha must be finite and > 0"); return PECNN_E_INVALID; }
   return PECNN_OK;
@@ -89,7 +100,7 @@ static int check_plan(const pecnn_plan* plan) {
 // ---------------------------------------------------------------- rollout graph cache
 struct GraphKey {
   const void* buf[4];
-  int len, with_ms, guard, ms_cfg, cnn_cfg, ch, prec, substeps;
+  int len, with_ms, guard, ms_cfg, cnn_cfg, ch, prec, cell, substeps;
   float dt, alpha;
   const float* theta;
   cloth_ms_params sim;
@@ -218,6 +229,11 @@ const char* pecnn_last_error(void) { return g_err; }
 int64_t pecnn_theta_size(int32_t ch) {
   if (ch <= 0 || ch > 64) return -1;
   return (int64_t)ch * 54 + 2 * (int64_t)ch * ch + 9 * (int64_t)ch + 3;
+}
+
+int64_t pecnn_cell_theta_size(int32_t cell, int32_t ch) {
+  if (cell == PECNN_CELL_PAIR) return ch == 12 ? 51 : -1;
+  return cell == PECNN_CELL_CONV ? pecnn_theta_size(ch) : -1;
 }
 
 static int check_desc(const pecnn_batch_desc* d) {
@@ -438,7 +454,7 @@ int pecnn_workspace_bytes(const pecnn_plan* p, const pecnn_model* m, int32_t whi
     case PECNN_WS_BACKWARD: {
       int rc = check_model(m);
       if (rc) return rc;
-      *bytes = align256(backward_ws_bytes(p, m->ch));
+      *bytes = align256(m->cell == PECNN_CELL_PAIR ? pair_backward_ws_bytes(p) : backward_ws_bytes(p, m->ch));
       return PECNN_OK;
     }
     case PECNN_WS_ROLLOUT: *bytes = rollout_layout(p, nullptr).bytes; return PECNN_OK;
@@ -485,8 +501,10 @@ int pecnn_backward(const pecnn_plan* p, const pecnn_model* m, const float* s_pre
   if (m->precision != PECNN_FP32) { set_error("backward needs an FP32 model"); return PECNN_E_UNSUPPORTED; }
   if (!s_prev || !s_cur || !g_next || !g_theta) { set_error("null state, gradient or theta gradient"); return PECNN_E_INVALID; }
   if (g_cur && g_prev && g_cur == g_prev) { set_error("g_cur and g_prev must differ"); return PECNN_E_INVALID; }
-  const size_t need = align256(backward_ws_bytes(p, m->ch));
+  const size_t need = align256(m->cell == PECNN_CELL_PAIR ? pair_backward_ws_bytes(p) : backward_ws_bytes(p, m->ch));
   if (!ws || ws_bytes < need) { set_error("backward workspace of %zu bytes needed", need); return PECNN_E_WORKSPACE; }
+  if (m->cell == PECNN_CELL_PAIR)  // the pair cell does not read S^{k-1}: g_prev gets nothing
+    return pair_backward_launch(p, m, s_cur, g_next, g_cur, g_theta, ws, (hipStream_t)stream);
   return backward_launch(p, m, s_prev, s_cur, g_next, g_cur, g_prev, g_theta, ws, (hipStream_t)stream);
 }
 
@@ -631,7 +649,7 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     memset(&key, 0, sizeof(key));
     key.buf[0] = buf[0]; key.buf[1] = buf[1]; key.buf[2] = buf[2]; key.buf[3] = w.T;
     key.len = len; key.with_ms = with_ms; key.guard = guard_on; key.ms_cfg = p->ms_cfg; key.cnn_cfg = p->cnn_cfg;
-    key.ch = m->ch; key.prec = m->precision; key.substeps = g->substeps; key.dt = m->dt; key.alpha = m->isru_alpha;
+    key.ch = m->ch; key.prec = m->precision; key.cell = m->cell; key.substeps = g->substeps; key.dt = m->dt; key.alpha = m->isru_alpha;
     key.theta = m->theta; key.sim = *simp; key.gd = *g; key.fallback = fallback; key.ws = ws;
     key.stats = stats_d;
     hipGraphExec_t exec = nullptr;

@@ -229,36 +229,13 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(
       accC[c] -= gus[fac_node(q, L.rows) + (c * 9 + o) * 32];
       accP[c] += gud[fac_node(q, L.rows) + (c * 9 + o) * 32];
     }
-  if (I.pres != 0.f) {
-    // the term c (x_j1 - x_P) x (x_j2 - x_P) of node P with adjoint l = dLoss/dv' (zero when P
-    // is pinned), c = dt p / m: d/dx_j1 = c (x_j2 - x_P) x l, d/dx_j2 = c l x (x_j1 - x_P),
-    // d/dx_P = minus both. Node q takes the parts where it is P, j1 or j2.
-    const int R[4][2] = {{0, 1}, {1, 0}, {0, -1}, {-1, 0}};  // right, down, left, up
-    const float c = dt * I.pres / I.mass;
-    for (int o = 0; o < 5; ++o) {
-      const int pi = qi + (o == 0 ? 0 : R[o - 1][0]), pj = qj + (o == 0 ? 0 : R[o - 1][1]);
-      if (pi < 0 || pi >= I.H || pj < 0 || pj >= I.W) continue;
-      const int64_t P = I.off + (int64_t)pi * I.W + pj;
-      const float l0 = fac[fac_node(P, L.rows) + (L.gdv + 0) * 32];
-      const float l1 = fac[fac_node(P, L.rows) + (L.gdv + 1) * 32];
-      const float l2 = fac[fac_node(P, L.rows) + (L.gdv + 2) * 32];
-      const float xp0 = s_cur[P], xp1 = s_cur[N + P], xp2 = s_cur[2 * N + P];
-      for (int k = 0; k < 4; ++k) {
-        const int i1 = pi + R[k][0], j1 = pj + R[k][1];
-        const int i2 = pi + R[(k + 1) & 3][0], j2 = pj + R[(k + 1) & 3][1];
-        if (i1 < 0 || i1 >= I.H || j1 < 0 || j1 >= I.W || i2 < 0 || i2 >= I.H || j2 < 0 || j2 >= I.W) continue;
-        const bool is1 = i1 == qi && j1 == qj, is2 = i2 == qi && j2 == qj;
-        if (o != 0 && !is1 && !is2) continue;
-        const int64_t q1 = I.off + (int64_t)i1 * I.W + j1, q2 = I.off + (int64_t)i2 * I.W + j2;
-        const float A0 = s_cur[q1] - xp0, A1 = s_cur[N + q1] - xp1, A2 = s_cur[2 * N + q1] - xp2;
-        const float B0 = s_cur[q2] - xp0, B1 = s_cur[N + q2] - xp1, B2 = s_cur[2 * N + q2] - xp2;
-        const float g10 = c * (B1 * l2 - B2 * l1), g11 = c * (B2 * l0 - B0 * l2), g12 = c * (B0 * l1 - B1 * l0);
-        const float g20 = c * (l1 * A2 - l2 * A1), g21 = c * (l2 * A0 - l0 * A2), g22 = c * (l0 * A1 - l1 * A0);
-        if (is1) { accC[0] += g10; accC[1] += g11; accC[2] += g12; }
-        if (is2) { accC[0] += g20; accC[1] += g21; accC[2] += g22; }
-        if (o == 0) { accC[0] -= g10 + g20; accC[1] -= g11 + g21; accC[2] -= g12 + g22; }
-      }
-    }
+  if (I.pres != 0.f) {  // eq. (3): the pressure terms that read x_q (dLoss/dv' of P from the table)
+    float acc[3] = {0.f, 0.f, 0.f};
+    auto gdv = [&](int64_t P, float (&l)[3]) {
+      for (int k = 0; k < 3; ++k) l[k] = fac[fac_node(P, L.rows) + (L.gdv + k) * 32];
+    };
+    pressure_adjoint_gather(I.H, I.W, I.off, qi, qj, dt * I.pres / I.mass, s_cur, N, gdv, acc);
+    for (int k = 0; k < 3; ++k) accC[k] += acc[k];
   }
   // eq. (5): x' = x + dt v', v' = C(v + dv + dt a)
 #pragma unroll
@@ -453,6 +430,167 @@ __global__ __launch_bounds__(1024) void wgrad_final_kernel(const float* __restri
     for (int k = 0; k < 16; ++k) t += sh[k][pl];
     g_theta[e] += (float)t;
   }
+}
+
+// ---------------------------------------------------------------- the pair cell
+// Reverse mode of the pair-cell frame (section 3.2 read literally; the PAIR mode of the stencil
+// kernel). For node P with l = dLoss/dv' (zero when P is pinned), a channel c whose neighbour j
+// is on the grid, and an axis a, with d = x_j - x_P, e = v_j - v_P, phi = s_c d, xi = s_c e:
+//   dLoss/dphi = l_a (wL_c + (wN_c + wD_c xi) sigma'(phi)),  dLoss/dxi = l_a wD_c sigma(phi);
+//   x_j gets + s_c dLoss/dphi and x_P gets - s_c dLoss/dphi (v likewise with dLoss/dxi);
+//   wL_c += l_a phi, wN_c += l_a sigma(phi), wD_c += l_a xi sigma(phi),
+//   s_c += dLoss/dphi d + dLoss/dxi e, b_L += l.
+// Two kernels: state gradients as a gather (each node collects the terms that read it), and
+// per-chunk parameter sums in fixed order, finished by wgrad_final_kernel. S^{k-1} is not read.
+constexpr int kPairP = 51;
+__device__ constexpr int kPairNb[12][2] = {{0, 1}, {0, -1}, {1, 0}, {-1, 0}, {1, 1}, {1, -1},
+                                           {-1, 1}, {-1, -1}, {0, 2}, {0, -2}, {2, 0}, {-2, 0}};
+
+__device__ __forceinline__ void pair_terms(const float* __restrict__ th, int c, float alpha, float d, float e, float l,
+                                           float& gphi, float& gxi, float& phi, float& xi, float& sg) {
+  const float sq = th[c], wl = th[12 + c], wn = th[24 + c], wd = th[36 + c];
+  phi = sq * d;
+  xi = sq * e;
+  const float r = __builtin_amdgcn_rsqf(__builtin_fmaf(alpha * phi, phi, 1.f));
+  sg = phi * r;
+  gphi = l * __builtin_fmaf(__builtin_fmaf(wd, xi, wn), r * r * r, wl);
+  gxi = l * (wd * sg);
+}
+
+__device__ __forceinline__ void pair_gdv(const uint8_t* __restrict__ pin, const float* __restrict__ g_next, int64_t N,
+                                         float dt, int64_t P, float (&l)[3]) {
+  const bool pinned = pin[P] != 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) l[k] = pinned ? 0.f : g_next[(3 + k) * N + P] + dt * g_next[k * N + P];
+}
+
+__global__ __launch_bounds__(256) void pair_gather_kernel(
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+    const uint8_t* __restrict__ pin, const float* __restrict__ s_cur, const float* __restrict__ g_next, int64_t N,
+    const float* __restrict__ theta, float alpha, float dt, float* __restrict__ g_cur) {
+  int b, local;
+  if (!chunk_node(inst, prefix, chunk_inst, blockIdx.x, b, local)) return;
+  const InstDev I = inst[b];
+  const int qi = local / I.W, qj = local - (local / I.W) * I.W;
+  const int64_t q = I.off + local;
+  float acc[6];
+  float lq[3];
+  pair_gdv(pin, g_next, N, dt, q, lq);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {  // eq. (5): x' = x + dt v', v' = C(v + dv + dt a)
+    acc[k] = g_next[k * N + q];
+    acc[3 + k] = lq[k];
+  }
+  float gphi, gxi, phi, xi, sg;
+  for (int c = 0; c < 12; ++c) {
+    // q as the centre of its channel c
+    const int ii = qi + kPairNb[c][0], jj = qj + kPairNb[c][1];
+    if (ii >= 0 && ii < I.H && jj >= 0 && jj < I.W) {
+      const int64_t j = I.off + (int64_t)ii * I.W + jj;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pair_terms(theta, c, alpha, s_cur[a * N + j] - s_cur[a * N + q], s_cur[(3 + a) * N + j] - s_cur[(3 + a) * N + q],
+                   lq[a], gphi, gxi, phi, xi, sg);
+        acc[a] -= theta[c] * gphi;
+        acc[3 + a] -= theta[c] * gxi;
+      }
+    }
+    // q as the channel-c neighbour of node P = q - o_c
+    const int pi = qi - kPairNb[c][0], pj = qj - kPairNb[c][1];
+    if (pi >= 0 && pi < I.H && pj >= 0 && pj < I.W) {
+      const int64_t P = I.off + (int64_t)pi * I.W + pj;
+      float lp[3];
+      pair_gdv(pin, g_next, N, dt, P, lp);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pair_terms(theta, c, alpha, s_cur[a * N + q] - s_cur[a * N + P], s_cur[(3 + a) * N + q] - s_cur[(3 + a) * N + P],
+                   lp[a], gphi, gxi, phi, xi, sg);
+        acc[a] += theta[c] * gphi;
+        acc[3 + a] += theta[c] * gxi;
+      }
+    }
+  }
+  if (I.pres != 0.f) {  // eq. (3): the pressure terms that read x_q
+    float ap[3] = {0.f, 0.f, 0.f};
+    auto gdv = [&](int64_t P, float (&l)[3]) { pair_gdv(pin, g_next, N, dt, P, l); };
+    pressure_adjoint_gather(I.H, I.W, I.off, qi, qj, dt * I.pres / I.mass, s_cur, N, gdv, ap);
+    for (int k = 0; k < 3; ++k) acc[k] += ap[k];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) g_cur[c * N + q] += acc[c];
+}
+
+__global__ __launch_bounds__(256) void pair_wgrad_kernel(
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+    const uint8_t* __restrict__ pin, const float* __restrict__ s_cur, const float* __restrict__ g_next, int64_t N,
+    const float* __restrict__ theta, float alpha, float dt, float* __restrict__ partial) {
+  __shared__ float sh[kPairP][4];
+  float g[kPairP];
+#pragma unroll
+  for (int k = 0; k < kPairP; ++k) g[k] = 0.f;
+  int b, local;
+  if (chunk_node(inst, prefix, chunk_inst, blockIdx.x, b, local)) {  // every thread joins the sums below
+    const InstDev I = inst[b];
+    const int qi = local / I.W, qj = local - (local / I.W) * I.W;
+    const int64_t q = I.off + local;
+    float l[3];
+    pair_gdv(pin, g_next, N, dt, q, l);
+    g[48] = l[0];
+    g[49] = l[1];
+    g[50] = l[2];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const int ii = qi + kPairNb[c][0], jj = qj + kPairNb[c][1];
+      if (ii < 0 || ii >= I.H || jj < 0 || jj >= I.W) continue;
+      const int64_t j = I.off + (int64_t)ii * I.W + jj;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float d = s_cur[a * N + j] - s_cur[a * N + q], e = s_cur[(3 + a) * N + j] - s_cur[(3 + a) * N + q];
+        float gphi, gxi, phi, xi, sg;
+        pair_terms(theta, c, alpha, d, e, l[a], gphi, gxi, phi, xi, sg);
+        g[c] = __builtin_fmaf(gxi, e, __builtin_fmaf(gphi, d, g[c]));
+        g[12 + c] = __builtin_fmaf(l[a], phi, g[12 + c]);
+        g[24 + c] = __builtin_fmaf(l[a], sg, g[24 + c]);
+        g[36 + c] = __builtin_fmaf(l[a], xi * sg, g[36 + c]);
+      }
+    }
+  }
+  // fixed-order block sums: butterfly within each wave, then the four wave sums
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kPairP; ++k) {
+    float v = g[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) sh[k][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPairP) {
+    const int k = threadIdx.x;
+    partial[(int64_t)blockIdx.x * kPairP + k] = ((sh[k][0] + sh[k][1]) + sh[k][2]) + sh[k][3];
+  }
+}
+
+size_t pair_backward_ws_bytes(const pecnn_plan* plan) {
+  return (size_t)plan->n_tiles[kCfgChunk] * kPairP * sizeof(float);
+}
+
+int pair_backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* sc, const float* gn, float* gc,
+                         float* gth, void* ws, hipStream_t st) {
+  const int nt = plan->n_tiles[kCfgChunk];
+  const int32_t* pre = plan->d_prefix[kCfgChunk];
+  float* partial = (float*)ws;
+  if (gc) {
+    hipLaunchKernelGGL(pair_gather_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin,
+                       sc, gn, plan->total, m->theta, m->isru_alpha, m->dt, gc);
+    PECNN_LAUNCH_CHECK("pair_gather_kernel");
+  }
+  hipLaunchKernelGGL(pair_wgrad_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, sc,
+                     gn, plan->total, m->theta, m->isru_alpha, m->dt, partial);
+  PECNN_LAUNCH_CHECK("pair_wgrad_kernel");
+  hipLaunchKernelGGL(wgrad_final_kernel, dim3(1), dim3(1024), 0, st, partial, nt, kPairP, gth);
+  PECNN_LAUNCH_CHECK("wgrad_final_kernel");
+  return PECNN_OK;
 }
 
 size_t backward_ws_bytes(const pecnn_plan* plan, int ch) {

@@ -178,9 +178,11 @@ static int dispatch_cfg(const pecnn_plan* plan, int cfg, const float* sp, const 
 
 int cnn_forward_bf16_launch(const pecnn_plan*, int, const pecnn_model*, const float*, const float*, float*,
                             const int32_t*, hipStream_t);
+int pair_forward_launch(const pecnn_plan*, const pecnn_model*, const float*, float*, const int32_t*, hipStream_t);
 
 int cnn_forward_launch(const pecnn_plan* plan, int cfg, const pecnn_model* m, const float* sp,
                        const float* sc, float* sn, const int32_t* skip, hipStream_t st) {
+  if (m->cell == PECNN_CELL_PAIR) return pair_forward_launch(plan, m, sc, sn, skip, st);
   if (m->precision == PECNN_BF16) return cnn_forward_bf16_launch(plan, cfg, m, sp, sc, sn, skip, st);
   int rc;
   if (m->ch == 16)

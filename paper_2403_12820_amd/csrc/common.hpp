@@ -132,6 +132,41 @@ __device__ __forceinline__ void pressure_pairs(const float (&d)[4][3], const boo
   }
 }
 
+// Adjoint of the eq. (3) term c (x_j1 - x_P) x (x_j2 - x_P) of every node P that reads the position
+// of node q = (qi, qj): q itself and its four nearest neighbours. For the adjoint l = dLoss/dv'
+// of P's velocity, d/dx_j1 = c (x_j2 - x_P) x l, d/dx_j2 = c l x (x_j1 - x_P), d/dx_P = minus both;
+// node q adds the parts where it is P, j1 or j2 into acc. gdv(P, l) gives P's adjoint (zero when P
+// is pinned); s_cur holds the positions (planes 0..2 of N floats); off is the instance's first node.
+template <typename Gdv>
+__device__ __forceinline__ void pressure_adjoint_gather(int H, int W, int64_t off, int qi, int qj, float c,
+                                                        const float* __restrict__ s_cur, int64_t N, Gdv gdv,
+                                                        float (&acc)[3]) {
+  const int R[4][2] = {{0, 1}, {1, 0}, {0, -1}, {-1, 0}};  // right, down, left, up
+  for (int o = 0; o < 5; ++o) {
+    const int pi = qi + (o == 0 ? 0 : R[o - 1][0]), pj = qj + (o == 0 ? 0 : R[o - 1][1]);
+    if (pi < 0 || pi >= H || pj < 0 || pj >= W) continue;
+    const int64_t P = off + (int64_t)pi * W + pj;
+    float l[3];
+    gdv(P, l);
+    const float xp0 = s_cur[P], xp1 = s_cur[N + P], xp2 = s_cur[2 * N + P];
+    for (int k = 0; k < 4; ++k) {
+      const int i1 = pi + R[k][0], j1 = pj + R[k][1];
+      const int i2 = pi + R[(k + 1) & 3][0], j2 = pj + R[(k + 1) & 3][1];
+      if (i1 < 0 || i1 >= H || j1 < 0 || j1 >= W || i2 < 0 || i2 >= H || j2 < 0 || j2 >= W) continue;
+      const bool is1 = i1 == qi && j1 == qj, is2 = i2 == qi && j2 == qj;
+      if (o != 0 && !is1 && !is2) continue;
+      const int64_t q1 = off + (int64_t)i1 * W + j1, q2 = off + (int64_t)i2 * W + j2;
+      const float A0 = s_cur[q1] - xp0, A1 = s_cur[N + q1] - xp1, A2 = s_cur[2 * N + q1] - xp2;
+      const float B0 = s_cur[q2] - xp0, B1 = s_cur[N + q2] - xp1, B2 = s_cur[2 * N + q2] - xp2;
+      const float g10 = c * (B1 * l[2] - B2 * l[1]), g11 = c * (B2 * l[0] - B0 * l[2]), g12 = c * (B0 * l[1] - B1 * l[0]);
+      const float g20 = c * (l[1] * A2 - l[2] * A1), g21 = c * (l[2] * A0 - l[0] * A2), g22 = c * (l[0] * A1 - l[1] * A0);
+      if (is1) { acc[0] += g10; acc[1] += g11; acc[2] += g12; }
+      if (is2) { acc[0] += g20; acc[1] += g21; acc[2] += g22; }
+      if (o == 0) { acc[0] -= g10 + g20; acc[1] -= g11 + g21; acc[2] -= g12 + g22; }
+    }
+  }
+}
+
 struct MsParamsDev {
   float k[3];     // spring constants per family
   float mu, drag;

@@ -21,11 +21,22 @@ __device__ constexpr Spring kSprings[12] = {
 // VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
 // so the tile rows load as 16-byte pieces; otherwise as single floats.
 // PRES: some instance of the batch has a pressure (eq. 3); the others skip it uniformly.
-template <int TX, int TY, int RY, bool VEC, bool PRES>
+// PAIR: instead of the springs, one frame of the paper's own cell read literally (section 3.2):
+// twelve channels, one per stencil neighbour j, phi_c = s_c (x_j - x), xi_c = s_c (v_j - v) with
+// the same frozen two-point filter on each axis (eq. 6; zero when j is off the grid), then per axis
+// dv = sum_c [wL_c phi_c + wN_c sigma(phi_c) + wD_c xi_c sigma(phi_c)] + b_L (eq. 7) and eq. (5)
+// with pins, wind and pressure. It has the springs' stencil, so it shares their tiles and halo.
+struct PairArgs {
+  const float* theta;    // s[12] | wL[12] | wN[12] | wD[12] | bL[3]
+  float alpha, dt;       // ISRU parameter, frame time step
+  const int32_t* skip;   // instances to leave alone (fallen back), or null
+};
+
+template <int TX, int TY, int RY, bool VEC, bool PRES, bool PAIR = false>
 __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_in, float* __restrict__ s_out,
-    int64_t N, MsParamsDev P, const uint8_t* __restrict__ active) {
+    int64_t N, MsParamsDev P, const uint8_t* __restrict__ active, PairArgs pa) {
   constexpr int NT = TX * (TY / RY);
   constexpr int RS = TX + 8;  // LDS row stride: tile column j at 4 + j, halo columns 2, 3 and 4+TX, 5+TX
   constexpr int HY = TY + 4;
@@ -57,8 +68,13 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
   const int t_end = first + count * stride;
   auto next_tile = [&](int t) -> int {
     while (t < t_end) {
-      cursor_seek(tcur, inst, prefix, n_inst, t, active);
-      if ((active == nullptr || tcur.flag != 0)) return t;
+      if constexpr (PAIR) {
+        cursor_seek(tcur, inst, prefix, n_inst, t, pa.skip);
+        if (tcur.flag == 0) return t;
+      } else {
+        cursor_seek(tcur, inst, prefix, n_inst, t, active);
+        if ((active == nullptr || tcur.flag != 0)) return t;
+      }
       t = first + ((tcur.end - first + stride - 1) / stride) * stride;
     }
     return -1;
@@ -177,7 +193,49 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
           const float x0 = lds[e], x1 = lds[PLN + e], x2 = lds[2 * PLN + e];
           const float v0 = lds[3 * PLN + e], v1 = lds[4 * PLN + e], v2 = lds[5 * PLN + e];
           float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-          if (!tP[ly * TX + tx]) {
+          if constexpr (PAIR) {
+            if (!tP[ly * TX + tx]) {
+              float acc[3] = {pa.theta[48], pa.theta[49], pa.theta[50]};  // b_L
+              const float xv[6] = {x0, x1, x2, v0, v1, v2};
+#pragma unroll
+              for (int q = 0; q < 12; ++q) {
+                const Spring S = kSprings[q];
+                const int ii = i + S.dy, jj = j + S.dx;
+                if (ii < 0 || ii >= Ic.H || jj < 0 || jj >= Ic.W) continue;  // no channel off the grid
+                const int en = e + S.dy * RS + S.dx;
+                const float sq = pa.theta[q], wl = pa.theta[12 + q], wn = pa.theta[24 + q], wd = pa.theta[36 + q];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                  const float phi = sq * (lds[a * PLN + en] - xv[a]);
+                  const float xi = sq * (lds[(3 + a) * PLN + en] - xv[3 + a]);
+                  const float sg = phi * __builtin_amdgcn_rsqf(__builtin_fmaf(pa.alpha * phi, phi, 1.f));
+                  acc[a] = __builtin_fmaf(wl, phi, acc[a]);
+                  acc[a] = __builtin_fmaf(wn, sg, acc[a]);
+                  acc[a] = __builtin_fmaf(wd * xi, sg, acc[a]);
+                }
+              }
+              n0 = (v0 + acc[0]) + pa.dt * Ic.ax;
+              n1 = (v1 + acc[1]) + pa.dt * Ic.ay;
+              n2 = (v2 + acc[2]) + pa.dt * Ic.az;
+              if constexpr (PRES) {
+                if (Ic.pres != 0.f) {  // eq. (3) at S^k, a known external force
+                  const int nb[4] = {1, RS, -1, -RS};  // right, down, left, up
+                  float d[4][3];
+#pragma unroll
+                  for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) d[k][a] = lds[a * PLN + e + nb[k]] - xv[a];
+                  const bool has[4] = {j + 1 < Ic.W, i + 1 < Ic.H, j > 0, i > 0};
+                  float p0, p1, p2;
+                  pressure_pairs(d, has, p0, p1, p2);
+                  const float cp = pa.dt * Ic.pres / Ic.mass;
+                  n0 = __builtin_fmaf(cp, p0, n0);
+                  n1 = __builtin_fmaf(cp, p1, n1);
+                  n2 = __builtin_fmaf(cp, p2, n2);
+                }
+              }
+            }
+          } else if (!tP[ly * TX + tx]) {
             float f0 = __builtin_fmaf(-P.drag, v0, g0);
             float f1 = __builtin_fmaf(-P.drag, v1, g1);
             float f2 = __builtin_fmaf(-P.drag, v2, g2);
@@ -224,12 +282,13 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
             n2 = __builtin_fmaf(sc, f2, v2);
           }
           const int N32 = (int)N;
+          const float dto = PAIR ? pa.dt : P.dt;
           gst(s_out, 3 * N32 + p, n0);
           gst(s_out, 4 * N32 + p, n1);
           gst(s_out, 5 * N32 + p, n2);
-          gst(s_out, p, __builtin_fmaf(P.dt, n0, x0));
-          gst(s_out, N32 + p, __builtin_fmaf(P.dt, n1, x1));
-          gst(s_out, 2 * N32 + p, __builtin_fmaf(P.dt, n2, x2));
+          gst(s_out, p, __builtin_fmaf(dto, n0, x0));
+          gst(s_out, N32 + p, __builtin_fmaf(dto, n1, x1));
+          gst(s_out, 2 * N32 + p, __builtin_fmaf(dto, n2, x2));
         }
       }
     }
@@ -254,7 +313,7 @@ static void launch_ms(const pecnn_plan* plan, int slot, const MsParamsDev& P, co
   const int grid = grid_for(n_tiles, 8);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TX * (TY / RY)), 0, st, plan->d_inst, plan->d_prefix[slot], plan->n,
-                       n_tiles, plan->pin, in, out, plan->total, P, active);
+                       n_tiles, plan->pin, in, out, plan->total, P, active, PairArgs{});
   };
   if (plan->has_pressure) {
     if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, true>);
@@ -263,6 +322,43 @@ static void launch_ms(const pecnn_plan* plan, int slot, const MsParamsDev& P, co
     if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, false>);
     else go(ms_step_kernel<TX, TY, RY, false, false>);
   }
+}
+
+template <int TX, int TY, int RY>
+static void launch_pair(const pecnn_plan* plan, int slot, const PairArgs& pa, const float* in, float* out,
+                        hipStream_t st) {
+  const int n_tiles = plan->n_tiles[slot];
+  const int grid = grid_for(n_tiles, 8);
+  const MsParamsDev P{};
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(TX * (TY / RY)), 0, st, plan->d_inst, plan->d_prefix[slot], plan->n,
+                       n_tiles, plan->pin, in, out, plan->total, P, (const uint8_t*)nullptr, pa);
+  };
+  if (plan->has_pressure) {
+    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, true, true>);
+    else go(ms_step_kernel<TX, TY, RY, false, true, true>);
+  } else {
+    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, false, true>);
+    else go(ms_step_kernel<TX, TY, RY, false, false, true>);
+  }
+}
+
+// One frame of the pair cell on the simulator's tiles (configuration plan->ms_cfg).
+int pair_forward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* sc, float* sn,
+                        const int32_t* skip, hipStream_t st) {
+  const int cfg = plan->ms_cfg;
+  const int slot = ms_cfg_slot(cfg);
+  const PairArgs pa{m->theta, m->isru_alpha, m->dt, skip};
+  switch (cfg) {
+    case 0: launch_pair<32, 8, 1>(plan, slot, pa, sc, sn, st); break;
+    case 1: launch_pair<64, 4, 1>(plan, slot, pa, sc, sn, st); break;
+    case 2: launch_pair<16, 16, 1>(plan, slot, pa, sc, sn, st); break;
+    case 3: launch_pair<32, 16, 2>(plan, slot, pa, sc, sn, st); break;
+    case 4: launch_pair<64, 8, 2>(plan, slot, pa, sc, sn, st); break;
+    default: return PECNN_E_INVALID;
+  }
+  PECNN_LAUNCH_CHECK("ms_step_kernel (pair cell)");
+  return PECNN_OK;
 }
 
 MsParamsDev ms_params_dev(const cloth_ms_params* p) {

@@ -229,6 +229,19 @@ def init_theta(ch: int, seed: int = 1, std: float = 0.02) -> np.ndarray:
     return (Stream(seed, TAG_THETA).normal(theta_size(ch)) * std).astype(np.float32)
 
 
+PAIR_THETA_SIZE = 51  # pair cell: s[12] | wL[12] | wN[12] | wD[12] | b_L[3]
+
+
+def init_pair_theta(seed: int = 1, std: float = 0.02, h: float = 1.0 / 31.0) -> np.ndarray:
+    """Pair cell: filter scales s_c = 1 / rest length of the channel's link (so that a link at
+    rest gives |phi| = 1 along it), branch weights N(0, std^2) in flat order, bias 0."""
+    th = Stream(seed, TAG_THETA).normal(PAIR_THETA_SIZE) * std
+    rest = np.array([1.0] * 4 + [math.sqrt(2.0)] * 4 + [2.0] * 4) * h
+    th[0:12] = 1.0 / rest
+    th[48:51] = 0.0
+    return th.astype(np.float32)
+
+
 def random_array(shape, seed: int, scale: float = 1.0, tag: int = TAG_MISC) -> np.ndarray:
     n = int(np.prod(shape))
     return (Stream(seed, tag).normal(n) * scale).reshape(shape)

@@ -104,17 +104,25 @@ class WindowBatch:
 
 
 class Trainer:
-    def __init__(self, ch=32, dt_nn=5e-3, lr=1e-3, theta=None, seed=1, device="cuda"):
+    """Adam on the cell's parameters. cell "conv": the channel-mixing convolution cell with ch
+    channels; cell "pair": section 3.2's own cell (12 frozen neighbour-difference channels)."""
+
+    def __init__(self, ch=32, dt_nn=5e-3, lr=1e-3, theta=None, seed=1, device="cuda", cell="conv"):
         import torch
         from . import _lib as L
-        self.ch, self.dt_nn, self.lr = ch, dt_nn, lr
-        th = I.init_theta(ch, seed=seed) if theta is None else np.asarray(theta, np.float32)
+        if cell == "pair":
+            ch = 12
+        self.ch, self.dt_nn, self.lr, self.cell = ch, dt_nn, lr, cell
+        if theta is not None:
+            th = np.asarray(theta, np.float32)
+        else:
+            th = I.init_pair_theta(seed) if cell == "pair" else I.init_theta(ch, seed=seed)
         self.theta = torch.tensor(th, device=device)
         self.m = torch.zeros_like(self.theta)
         self.v = torch.zeros_like(self.theta)
         self.g = torch.zeros_like(self.theta)
         self.t = 0
-        self.model = L.make_model(self.theta, ch, L.PECNN_FP32, dt=dt_nn)
+        self.model = L.make_model(self.theta, ch, L.PECNN_FP32, dt=dt_nn, cell=cell_code(cell))
         self.device = device
 
     def _buffers(self, plan, U, N, phys=False):
@@ -203,7 +211,13 @@ def eval_loss(tr: Trainer, wb: WindowBatch, plan, n_free, sx, sv, one_step_weigh
     return float(loss.item())
 
 
-def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0, dt_nn=5e-3, device="cuda"):
+def cell_code(cell):
+    from . import _lib as L
+    return {"conv": L.CELL_CONV, "pair": L.CELL_PAIR}[cell]
+
+
+def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0, dt_nn=5e-3, device="cuda",
+                cell="conv"):
     """Network rollout of n_frames from frame 0 (S^{-1} = S^0) of the given scenes; position RMS
     against the saved simulator frame n_frames, per scene, divided by the cloth width (FP64
     reduction kernel)."""
@@ -213,7 +227,7 @@ def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0,
     batch = I.make_batch(sc)
     plan = L.Plan.from_batch(batch, device)
     th = torch.tensor(np.asarray(theta, np.float32), device=device)
-    model = L.make_model(th, ch, precision, dt=dt_nn)
+    model = L.make_model(th, ch, precision, dt=dt_nn, cell=cell_code(cell))
     idx = np.concatenate([np.arange(traj.batch.node_off[b], traj.batch.node_off[b + 1]) for b in scene_ids])
     idx_t = torch.tensor(idx, device=device)
     s0 = traj.frames[0][:, idx_t].contiguous()
@@ -234,7 +248,7 @@ def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0,
 
 def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=32, lr=1e-3, seed=4,
           n_frames=201, stride=10, log_every=500, eval_frames=100, device="cuda", verbose=True, lr_final=None,
-          alpha=0.0):
+          alpha=0.0, cell="conv"):
     """Adam at lr, annealed along a cosine to lr_final over the run when lr_final is given (the
     post-process cosine schedule of Table 1); alpha weighs the physics term of eq. (8)."""
     import torch
@@ -247,7 +261,8 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     train_ids = list(range(n_scenes - n_val))
     val_ids = list(range(n_scenes - n_val, n_scenes))
     wb = WindowBatch(traj, train_ids, n_win, n_unroll, device)
-    tr = Trainer(ch=ch, dt_nn=stride * mat.dt, lr=lr, device=device)
+    tr = Trainer(ch=ch, dt_nn=stride * mat.dt, lr=lr, device=device, cell=cell)
+    ch = tr.ch
     theta0 = tr.theta.cpu().numpy().copy()
     rng = np.random.default_rng(seed)
     # fixed held-out windows for a deterministic validation loss
@@ -267,7 +282,7 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
             if not np.isfinite(lv):
                 raise FloatingPointError("training diverged at iteration %d" % it)
             rms_v, _ = rollout_rms(traj, val_ids, tr.theta.cpu().numpy(), ch, eval_frames, dt_nn=stride * mat.dt,
-                                   device=device)
+                                   device=device, cell=cell)
             if rms_v.mean() < best[0]:
                 best = (float(rms_v.mean()), tr.theta.cpu().numpy().copy())
             if verbose:
@@ -277,14 +292,16 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     torch.cuda.synchronize()
     t_train = time.time() - t1
     theta_best = best[1]
-    rms_trained, _ = rollout_rms(traj, val_ids, theta_best, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
-    rms_untrained, _ = rollout_rms(traj, val_ids, theta0, ch, eval_frames, dt_nn=stride * mat.dt, device=device)
+    rms_trained, _ = rollout_rms(traj, val_ids, theta_best, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
+                                 cell=cell)
+    rms_untrained, _ = rollout_rms(traj, val_ids, theta0, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
+                                   cell=cell)
     val_loss_final = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
     tr.theta.copy_(torch.tensor(theta_best, device=device))
     val_loss_best = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
     report = {
         "scenes": n_scenes, "grid": size, "val_scenes": n_val, "iters": iters, "minibatch": n_win,
-        "unroll": n_unroll, "channels": ch, "lr": lr, "lr_final": lr_final, "alpha": alpha, "stride": stride,
+        "unroll": n_unroll, "cell": cell, "channels": ch, "lr": lr, "lr_final": lr_final, "alpha": alpha, "stride": stride,
         "frames": n_frames,
         "increment_scales": [sx, sv], "loss_curve": curve, "generation_s": t_gen, "train_s": t_train,
         "val_rms_trained": rms_trained.tolist(), "val_rms_untrained": rms_untrained.tolist(),
@@ -308,12 +325,14 @@ def main():
     ap.add_argument("--lr-final", type=float, default=None)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--alpha", type=float, default=0.0, help="weight of the physics term of eq. (8)")
+    ap.add_argument("--cell", choices=("conv", "pair"), default="conv")
     ap.add_argument("--log-every", type=int, default=500)
     ap.add_argument("--out", default=os.path.join(HERE, "weights", "pecnn_ch32.npy"))
     ap.add_argument("--report", default=None)
     args = ap.parse_args()
     theta, report = train(args.scenes, args.size, args.val, args.iters, args.minibatch, args.unroll, args.ch,
-                          args.lr, args.seed, log_every=args.log_every, lr_final=args.lr_final, alpha=args.alpha)
+                          args.lr, args.seed, log_every=args.log_every, lr_final=args.lr_final, alpha=args.alpha,
+                          cell=args.cell)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, theta.astype(np.float32), allow_pickle=False)
     rep = args.report or os.path.splitext(args.out)[0] + "_report.json"
