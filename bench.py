@@ -15,6 +15,10 @@ Printed (one JSON line): the contract fields, plus
                   summary when it was taken on the current kernel source, else null;
   cpu_baseline  - the FP64 oracle's CNN frame on a bounded sample, single thread;
   config        - the workload, raw frame rate, mass-spring rate, RMS and fallbacks.
+
+--cell pair runs section 3.2's own cell read literally instead (twelve frozen
+neighbour-difference channels, FP32, on the mass-spring step's tiles) with its trained weights;
+the default line is the bf16 convolution cell.
 """
 from __future__ import annotations
 
@@ -32,9 +36,11 @@ sys.path.insert(0, ROOT)
 METRIC = "cloth node-steps/s: BF16 CNN rollout vs FP32 mass-spring, at fixed RMS error"
 HBM_PEAK_GBS = 8000.0
 CNN_BYTES_PER_NODE = 73  # read S^k and S^{k-1} (24 B each), write S^{k+1} (24 B), pin flag (1 B)
+PAIR_BYTES_PER_NODE = 49  # the pair cell reads S^k only: 24 B + pin flag, writes 24 B
 MS_BYTES_PER_NODE = 49   # read S (24 B), write S' (24 B), pin flag (1 B)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cnn_fwd_bf16_128x256x256_traffic.txt")
 WEIGHTS = os.path.join(ROOT, "paper_2403_12820_amd", "weights", "pecnn_ch32.npy")
+PAIR_WEIGHTS = os.path.join(ROOT, "paper_2403_12820_amd", "weights", "pecnn_pair.npy")
 CNN_TILES = {0: "64, 4", 1: "32, 8", 2: "16, 16", 3: "64, 8"}
 
 
@@ -49,8 +55,14 @@ def measured_traffic(nodes):
     return float(tr["bytes_per_launch"])
 
 
-def load_theta(ch):
+def load_theta(ch, cell="conv"):
     from paper_2403_12820_amd import inputs as I
+    if cell == "pair":
+        if os.path.exists(PAIR_WEIGHTS):
+            th = np.load(PAIR_WEIGHTS, allow_pickle=False).astype(np.float32)
+            if th.size == I.PAIR_THETA_SIZE:
+                return th, "trained"
+        return I.init_pair_theta(seed=1), "initial (s = 1/L, weights N(0, 0.02) seed 1)"
     if ch == 32 and os.path.exists(WEIGHTS):
         th = np.load(WEIGHTS, allow_pickle=False).astype(np.float32)
         if th.size == I.theta_size(ch):
@@ -58,7 +70,7 @@ def load_theta(ch):
     return I.init_theta(ch, seed=1), "random N(0, 0.02) seed 1"
 
 
-def cpu_baseline(ch, theta, budget_s=10.0):
+def cpu_baseline(ch, theta, budget_s=10.0, cell="conv"):
     """The FP64 oracle's CNN frame on one 256 x 256 cloth, repeated for about budget_s seconds."""
     import oracle
     from paper_2403_12820_amd import inputs as I
@@ -69,14 +81,18 @@ def cpu_baseline(ch, theta, budget_s=10.0):
     frames = 0
     sp, sk = s, s
     while True:
-        sn, _ = oracle.cnn_forward(256, 256, ch, 1.0, 5e-3, sc.a_ext, sc.pin, th, sp, sk)
+        if cell == "pair":
+            sn, _ = oracle.pair_forward(256, 256, 1.0, 5e-3, sc.a_ext, sc.pin, th, sk)
+        else:
+            sn, _ = oracle.cnn_forward(256, 256, ch, 1.0, 5e-3, sc.a_ext, sc.pin, th, sp, sk)
         sp, sk = sk, sn
         frames += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
     return {"value": frames * 256 * 256 / dt, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d FP64 CNN frames (Ch=%d) of one 256x256 cloth, single thread, %.1f s" % (frames, ch, dt)}
+            "sample": "%d FP64 %s frames of one 256x256 cloth, single thread, %.1f s" % (
+                frames, "pair-cell" if cell == "pair" else "CNN (Ch=%d)" % ch, dt)}
 
 
 def main():
@@ -97,6 +113,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cell", choices=("conv", "pair"), default="conv",
+                    help="conv: the bf16 convolution cell (default); pair: the paper's own cell, FP32")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (instances would shard "
@@ -123,9 +141,14 @@ def main():
     batch = I.make_batch(scenes)
     N = batch.total
     plan = L.Plan.from_batch(batch, dev)
-    theta_np, theta_kind = load_theta(args.ch)
+    pair = args.cell == "pair"
+    ch = 12 if pair else args.ch
+    theta_np, theta_kind = load_theta(ch, args.cell)
     theta = torch.tensor(theta_np, device=dev)
-    model = L.make_model(theta, args.ch, L.PECNN_BF16, dt=dt_nn)
+    if pair:
+        model = L.make_model(theta, 12, L.PECNN_FP32, dt=dt_nn, cell=L.CELL_PAIR)
+    else:
+        model = L.make_model(theta, ch, L.PECNN_BF16, dt=dt_nn)
     sim = L.ms_params(mat)
     s0 = torch.tensor(batch.state, device=dev)
     a, b, c = s0.clone(), s0.clone(), torch.empty_like(s0)
@@ -194,10 +217,10 @@ def main():
     ms_e1.record(st)
     torch.cuda.synchronize()
     t_ms_kernel = ms_e0.elapsed_time(ms_e1) / 1e3 / args.kernel_reps
-    alg_bytes = CNN_BYTES_PER_NODE * N
+    alg_bytes = (PAIR_BYTES_PER_NODE if pair else CNN_BYTES_PER_NODE) * N
     achieved = alg_bytes / t_kernel / 1e9
 
-    traffic = measured_traffic(N) if args.workload == "uniform" else None
+    traffic = measured_traffic(N) if args.workload == "uniform" and not pair else None
 
     raw = N * args.steps / t_roll
     value = raw * stride
@@ -205,13 +228,15 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * t_roll / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if pair else "bf16", "data": "synthetic",
         "config": {
-            "workload": "bf16 CNN rollout (Ch=%d) of %s, %d frames of %d simulator steps, guard + FP64 "
-                        "reductions every %d frames" % (args.ch, workload, args.steps, stride, args.check_every),
+            "workload": "%s rollout of %s, %d frames of %d simulator steps, guard + FP64 reductions every %d "
+                        "frames" % ("FP32 pair-cell (the paper's own cell, 12 channels)" if pair else
+                                    "bf16 CNN (Ch=%d)" % ch, workload, args.steps, stride, args.check_every),
+            "cell": args.cell,
             "instances": batch.n, "grid": ([args.size, args.size] if args.workload == "uniform" else
                                           [int(batch.H.min()), int(batch.H.max())]),
-            "nodes": N, "channels": args.ch,
+            "nodes": N, "channels": ch,
             "weights": theta_kind, "tiles": {"ms_cfg": ms_cfg, "cnn_cfg": cnn_cfg},
             "frame_dt": dt_nn, "sim_dt": mat.dt, "stride": stride,
             "raw_frames_node_steps_per_s": raw,
@@ -229,11 +254,12 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "cnn_fwd_bf16_kernel<32, %s>" % CNN_TILES.get(cnn_cfg, "?"),
+                     "kernel": ("ms_step_kernel (pair-cell frame, cfg %d)" % ms_cfg if pair else
+                                "cnn_fwd_bf16_kernel<32, %s>" % CNN_TILES.get(cnn_cfg, "?")),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.ch, theta_np, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(ch, theta_np, args.cpu_seconds, args.cell)
     plan.close()
     print(json.dumps(out))
 
