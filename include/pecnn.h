@@ -86,6 +86,17 @@ int pecnn_plan_get_tiles(const pecnn_plan* plan, int32_t* ms_cfg, int32_t* cnn_c
    rollout's cached graphs when the set of kernels changes. */
 int pecnn_plan_set_pressure(pecnn_plan* plan, const float* pressure, void* stream);
 
+/* A sphere per instance in the constraint operator C of eq. (5) (section 3.1: cloth-object
+   collision handled by intersection elimination; the ball absorbs the bounce and its friction
+   resists relative motion). sphere: host float [n][5] = centre x, y, z, radius R (>= 0; 0 = no
+   sphere, the default of a new plan), friction f in [0, 1]. For a free node with velocity v'
+   after the rest of eq. (5), y = x + dt v'; if |y - c| < R the node moves to c + R n,
+   n = (y - c)/|y - c| (n = +z when y = c), the inward part of v'.n is removed and the
+   tangential part of v' is scaled by 1 - f. Applies to the mass-spring step and to every frame
+   (pecnn_forward, pecnn_rollout); pecnn_backward returns PECNN_E_UNSUPPORTED for a plan with a
+   sphere. Synchronous on `stream`; drops the rollout's cached graphs when the kernels change. */
+int pecnn_plan_set_spheres(pecnn_plan* plan, const float* sphere, void* stream);
+
 /* ------------------------------------------------------------------ mass-spring step */
 
 /* Material and integration parameters of the mass-spring model (section 3.1). */

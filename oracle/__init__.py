@@ -8,7 +8,8 @@ compiles it with gcc and marshals numpy arrays through ctypes. Every function
 works on one cloth instance at a time; the batch helpers loop over instances.
 
 Paper passages followed (section / equation):
-  ms_force, ms_step, ms_run  - section 3.1, eqs. (1), (2), (3), (4), (5)
+  ms_force, ms_step, ms_run  - section 3.1, eqs. (1), (2), (3), (4), (5); the constraint of
+                               eq. (5) also handles a sphere (intersection elimination, friction)
   cnn_forward                - section 3.2, eqs. (6), (7), then (5) (Fig. 2), with wind and the
                                pressure of eq. (3) as known external forces
   cnn_backward               - section 3.2.1, reverse mode of the above
@@ -51,8 +52,8 @@ def _load():
         _lib = C.CDLL(_LIB)
         d, i, l, p = C.c_double, C.c_int, C.c_long, C.c_void_p
         _lib.or_ms_force.argtypes = [i, i, d, d, p, d, p, p, p, p]
-        _lib.or_ms_step.argtypes = [i, i, d, d, p, d, p, p, p, p]
-        _lib.or_ms_run.argtypes = [i, i, d, d, p, d, p, p, p, i]
+        _lib.or_ms_step.argtypes = [i, i, d, d, p, d, p, p, p, p, p]
+        _lib.or_ms_run.argtypes = [i, i, d, d, p, d, p, p, p, i, p]
         _lib.or_energy.argtypes = [i, i, d, d, p, p, p]
         _lib.or_energy.restype = d
         _lib.or_max_stretch.argtypes = [i, i, d, p, i]
@@ -61,11 +62,11 @@ def _load():
         _lib.or_sq_pos_err.restype = d
         _lib.or_theta_size.argtypes = [i]
         _lib.or_theta_size.restype = l
-        _lib.or_cnn_forward.argtypes = [i, i, i, d, d, p, d, p, p, p, p, p, i, p]
+        _lib.or_cnn_forward.argtypes = [i, i, i, d, d, p, d, p, p, p, p, p, i, p, p]
         _lib.or_cnn_backward.argtypes = [i, i, i, d, d, d, p, p, p, p, p, p, p, p]
         _lib.or_pair_theta_size.argtypes = []
         _lib.or_pair_theta_size.restype = l
-        _lib.or_pair_forward.argtypes = [i, i, d, d, p, d, p, p, p, p, p]
+        _lib.or_pair_forward.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p]
         _lib.or_pair_backward.argtypes = [i, i, d, d, d, p, p, p, p, p, p]
         _lib.or_loss_mse.argtypes = [l, p, l, d, d, d, p, p, p]
         _lib.or_loss_mse.restype = d
@@ -107,18 +108,25 @@ def ms_force(H, W, h, m, a_ext, pin, s, mat, pressure=0.0):
     return f
 
 
-def ms_step(H, W, h, m, a_ext, pin, s, mat, dt=None, pressure=0.0):
+def _sphere(sphere):
+    """(cx, cy, cz, R, friction) as a float64 array, or None for no sphere."""
+    return None if sphere is None else _f64(sphere).reshape(5)
+
+
+def ms_step(H, W, h, m, a_ext, pin, s, mat, dt=None, pressure=0.0, sphere=None):
     s = _f64(s).reshape(6, H * W)
     out = np.empty_like(s)
-    a, pn, P = _f64(a_ext), _u8(pin), ms_params(mat, dt)
-    _load().or_ms_step(H, W, h, m, _ptr(a), float(pressure), C.byref(P), _ptr(pn), _ptr(s), _ptr(out))
+    a, pn, P, sp = _f64(a_ext), _u8(pin), ms_params(mat, dt), _sphere(sphere)
+    _load().or_ms_step(H, W, h, m, _ptr(a), float(pressure), C.byref(P), _ptr(pn), _ptr(s), _ptr(out),
+                       _ptr(sp) if sp is not None else None)
     return out
 
 
-def ms_run(H, W, h, m, a_ext, pin, s, mat, n_steps, dt=None, pressure=0.0):
+def ms_run(H, W, h, m, a_ext, pin, s, mat, n_steps, dt=None, pressure=0.0, sphere=None):
     s = _f64(s).reshape(6, H * W).copy()
-    a, pn, P = _f64(a_ext), _u8(pin), ms_params(mat, dt)
-    _load().or_ms_run(H, W, h, m, _ptr(a), float(pressure), C.byref(P), _ptr(pn), _ptr(s), int(n_steps))
+    a, pn, P, sp = _f64(a_ext), _u8(pin), ms_params(mat, dt), _sphere(sphere)
+    _load().or_ms_run(H, W, h, m, _ptr(a), float(pressure), C.byref(P), _ptr(pn), _ptr(s), int(n_steps),
+                      _ptr(sp) if sp is not None else None)
     return s
 
 
@@ -142,7 +150,7 @@ def theta_size(ch) -> int:
     return int(_load().or_theta_size(ch))
 
 
-def cnn_forward(H, W, ch, alpha, dt, a_ext, pin, theta, s_prev, s_cur, emu=0, pm=0.0):
+def cnn_forward(H, W, ch, alpha, dt, a_ext, pin, theta, s_prev, s_cur, emu=0, pm=0.0, sphere=None):
     """Returns (s_next [6, n], dv [3, n]). emu: bf16 operand-rounding flags (0 = exact FP64);
     pm: pressure per unit node mass (eq. 3 force / m)."""
     sp, sc = _f64(s_prev).reshape(6, H * W), _f64(s_cur).reshape(6, H * W)
@@ -150,8 +158,9 @@ def cnn_forward(H, W, ch, alpha, dt, a_ext, pin, theta, s_prev, s_cur, emu=0, pm
     assert th.size == theta_size(ch) and ch <= 64
     out = np.empty((6, H * W))
     dv = np.empty((3, H * W))
+    sph = _sphere(sphere)
     _load().or_cnn_forward(H, W, ch, alpha, dt, _ptr(a), float(pm), _ptr(pn), _ptr(th), _ptr(sp), _ptr(sc),
-                           _ptr(out), int(emu), _ptr(dv))
+                           _ptr(out), int(emu), _ptr(dv), _ptr(sph) if sph is not None else None)
     return out, dv
 
 
@@ -169,13 +178,15 @@ def pair_theta_size() -> int:
     return int(_load().or_pair_theta_size())
 
 
-def pair_forward(H, W, alpha, dt, a_ext, pin, theta, s_cur, pm=0.0):
+def pair_forward(H, W, alpha, dt, a_ext, pin, theta, s_cur, pm=0.0, sphere=None):
     """The paper's pair cell, one frame: returns (s_next [6, n], dv [3, n])."""
     sc = _f64(s_cur).reshape(6, H * W)
     th, a, pn = _f64(theta), _f64(a_ext), _u8(pin)
     assert th.size == pair_theta_size()
     out, dv = np.empty((6, H * W)), np.empty((3, H * W))
-    _load().or_pair_forward(H, W, alpha, dt, _ptr(a), float(pm), _ptr(pn), _ptr(th), _ptr(sc), _ptr(out), _ptr(dv))
+    sph = _sphere(sphere)
+    _load().or_pair_forward(H, W, alpha, dt, _ptr(a), float(pm), _ptr(pn), _ptr(th), _ptr(sc), _ptr(out), _ptr(dv),
+                            _ptr(sph) if sph is not None else None)
     return out, dv
 
 
@@ -215,13 +226,20 @@ def _pressure(batch, b):
     return 0.0 if p is None else float(p[b])
 
 
+def _batch_sphere(batch, b):
+    sp = getattr(batch, "sphere", None)
+    if sp is None or not float(sp[b][3]) > 0.0:
+        return None
+    return np.asarray(sp[b], np.float64)
+
+
 def batch_ms_step(batch, s, mat, n_steps=1, dt=None):
     s = _f64(s)
     out = np.empty_like(s)
     for b in range(batch.n):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
-        out[:, sl] = ms_run(H, W, h, m, a, pin, s[:, sl], mat, n_steps, dt, _pressure(batch, b))
+        out[:, sl] = ms_run(H, W, h, m, a, pin, s[:, sl], mat, n_steps, dt, _pressure(batch, b), _batch_sphere(batch, b))
     return out
 
 
@@ -233,7 +251,7 @@ def batch_cnn_forward(batch, ch, alpha, dt, theta, s_prev, s_cur, emu=0):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
         out[:, sl], dv[:, sl] = cnn_forward(H, W, ch, alpha, dt, a, pin, theta, s_prev[:, sl],
-                                            s_cur[:, sl], emu, _pressure(batch, b) / m)
+                                            s_cur[:, sl], emu, _pressure(batch, b) / m, _batch_sphere(batch, b))
     return out, dv
 
 
@@ -259,7 +277,8 @@ def batch_pair_forward(batch, alpha, dt, theta, s_cur):
     for b in range(batch.n):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
-        out[:, sl], dv[:, sl] = pair_forward(H, W, alpha, dt, a, pin, theta, s_cur[:, sl], _pressure(batch, b) / m)
+        out[:, sl], dv[:, sl] = pair_forward(H, W, alpha, dt, a, pin, theta, s_cur[:, sl], _pressure(batch, b) / m,
+                                             _batch_sphere(batch, b))
     return out, dv
 
 

@@ -10,7 +10,8 @@
  *   - mass-spring step: section 3.1, eqs. (1) elastic spring force, (2) spring
  *     damping, (3) uniform pressure on the four nearest neighbours, (4) gravity
  *     and air drag, (5) semi-implicit Euler with the constraint operator
- *     (Dirichlet pins);
+ *     (Dirichlet pins, and a sphere handled by intersection elimination with
+ *     friction);
  *   - physics-embedded CNN cell: section 3.2, eq. (6) one shared convolution
  *     applied to the state and to its time derivative, eq. (7) linear, nonlinear
  *     (ISRU) and derivative branches summed into a velocity increment, then
@@ -115,30 +116,72 @@ void or_ms_force(int H, int W, double h, double m, const double *a_ext, double p
         }
 }
 
-/* One step of eq. (5): v' = C(v + dt f / m), x' = x + dt v'; C zeroes pinned velocities. */
+/* The position update of eq. (5), x' = x + dt v', for a free node, with the constraint operator C
+   extended by a sphere (section 3.1: cloth-object collision handled by intersection elimination;
+   the ball of the fourth scene absorbs the bounce and its friction resists relative motion).
+   If x + dt v lies inside the sphere (|y - c| < R), the node moves to the nearest surface point
+   c + R n, n = (y - c)/|y - c|, its inward normal velocity is removed and its tangential velocity
+   is scaled by 1 - fric. sphere = {cx, cy, cz, R, fric}; NULL or R <= 0: no sphere. v is in/out. */
+static void or_sphere_update(const double *sphere, double dt, const double *x, double *v, double *y)
+{
+    for (int a = 0; a < 3; ++a) y[a] = x[a] + dt * v[a];
+    if (!sphere || !(sphere[3] > 0.0)) return;
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = y[a] - sphere[a];
+    const double r = sqrt(or_dot3(d, d));
+    if (!(r < sphere[3])) return;
+    double nn[3] = {0.0, 0.0, 1.0};
+    if (r > 0.0)
+        for (int a = 0; a < 3; ++a) nn[a] = d[a] / r;
+    const double vn = or_dot3(v, nn);
+    for (int a = 0; a < 3; ++a) {
+        const double vt = v[a] - vn * nn[a];
+        v[a] = (1.0 - sphere[4]) * vt + (vn > 0.0 ? vn : 0.0) * nn[a];
+        y[a] = sphere[a] + sphere[3] * nn[a];
+    }
+}
+
+/* Writes node p of eq. (5): velocity v' (zero when pinned) and position, with the sphere. */
+static void or_store_node(long n, long p, int pinned, double dt, const double *s, double *v,
+                          const double *sphere, double *out)
+{
+    double x[3], y[3];
+    for (int a = 0; a < 3; ++a) x[a] = s[a * n + p];
+    if (pinned) {
+        for (int a = 0; a < 3; ++a) { v[a] = 0.0; y[a] = x[a] + dt * v[a]; }
+    } else {
+        or_sphere_update(sphere, dt, x, v, y);
+    }
+    for (int a = 0; a < 3; ++a) {
+        out[(3 + a) * n + p] = v[a];
+        out[a * n + p] = y[a];
+    }
+}
+
+/* One step of eq. (5): v' = C(v + dt f / m), x' = x + dt v'; C zeroes pinned velocities and
+   handles the sphere. */
 void or_ms_step(int H, int W, double h, double m, const double *a_ext, double pr, const or_ms_params *P,
-                const uint8_t *pin, const double *s, double *out)
+                const uint8_t *pin, const double *s, double *out, const double *sphere)
 {
     const long n = (long)H * W;
     double *f = (double *)malloc(sizeof(double) * 3 * n);
     or_ms_force(H, W, h, m, a_ext, pr, P, pin, s, f);
-    for (long p = 0; p < n; ++p)
-        for (int a = 0; a < 3; ++a) {
-            const double v = pin[p] ? 0.0 : s[(3 + a) * n + p] + P->dt * f[a * n + p] / m;
-            out[(3 + a) * n + p] = v;
-            out[a * n + p] = s[a * n + p] + P->dt * v;
-        }
+    for (long p = 0; p < n; ++p) {
+        double v[3];
+        for (int a = 0; a < 3; ++a) v[a] = s[(3 + a) * n + p] + P->dt * f[a * n + p] / m;
+        or_store_node(n, p, pin[p], P->dt, s, v, sphere, out);
+    }
     free(f);
 }
 
 /* n_steps consecutive steps; s is overwritten with the final state. */
 void or_ms_run(int H, int W, double h, double m, const double *a_ext, double pr, const or_ms_params *P,
-               const uint8_t *pin, double *s, int n_steps)
+               const uint8_t *pin, double *s, int n_steps, const double *sphere)
 {
     const long n = (long)H * W;
     double *t = (double *)malloc(sizeof(double) * 6 * n);
     for (int k = 0; k < n_steps; ++k) {
-        or_ms_step(H, W, h, m, a_ext, pr, P, pin, s, t);
+        or_ms_step(H, W, h, m, a_ext, pr, P, pin, s, t, sphere);
         memcpy(s, t, sizeof(double) * 6 * n);
     }
     free(t);
@@ -353,7 +396,7 @@ static double *or_time_diff(long n, const double *sp, const double *sk, int emu)
    x' = x + dt v'. */
 void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double *a_ext, double pm,
                     const uint8_t *pin, const double *theta, const double *s_prev,
-                    const double *s_cur, double *s_next, int emu, double *dv_out)
+                    const double *s_cur, double *s_next, int emu, double *dv_out, const double *sphere)
 {
     const long n = (long)H * W;
     const or_layout Lo = or_theta_layout(ch);
@@ -365,12 +408,12 @@ void or_cnn_forward(int H, int W, int ch, double alpha, double dt, const double 
             or_cell_node(H, W, ch, alpha, theta, &Lo, s_cur, dS, i, j, emu, o);
             double fp[3] = {0.0, 0.0, 0.0};
             if (pm != 0.0) or_pressure(H, W, s_cur, i, j, dt * pm, fp);
+            double v[3];
             for (int a = 0; a < 3; ++a) {
                 if (dv_out) dv_out[a * n + p] = o->dv[a];
-                const double v = pin[p] ? 0.0 : s_cur[(3 + a) * n + p] + o->dv[a] + dt * a_ext[a] + fp[a];
-                s_next[(3 + a) * n + p] = v;
-                s_next[a * n + p] = s_cur[a * n + p] + dt * v;
+                v[a] = s_cur[(3 + a) * n + p] + o->dv[a] + dt * a_ext[a] + fp[a];
             }
+            or_store_node(n, p, pin[p], dt, s_cur, v, sphere, s_next);
         }
     free(o);
     free(dS);
@@ -519,7 +562,7 @@ static void or_pair_node(int H, int W, double alpha, const double *th, const dou
 /* One frame with the pair cell: v' = C(v + dv + dt a_ext + dt pm f_p(x)), x' = x + dt v'. */
 void or_pair_forward(int H, int W, double alpha, double dt, const double *a_ext, double pm,
                      const uint8_t *pin, const double *theta, const double *s_cur, double *s_next,
-                     double *dv_out)
+                     double *dv_out, const double *sphere)
 {
     const long n = (long)H * W;
     for (int i = 0; i < H; ++i)
@@ -528,12 +571,12 @@ void or_pair_forward(int H, int W, double alpha, double dt, const double *a_ext,
             double dv[3], fp[3] = {0.0, 0.0, 0.0};
             or_pair_node(H, W, alpha, theta, s_cur, i, j, dv);
             if (pm != 0.0) or_pressure(H, W, s_cur, i, j, dt * pm, fp);
+            double v[3];
             for (int a = 0; a < 3; ++a) {
                 if (dv_out) dv_out[a * n + p] = dv[a];
-                const double v = pin[p] ? 0.0 : s_cur[(3 + a) * n + p] + dv[a] + dt * a_ext[a] + fp[a];
-                s_next[(3 + a) * n + p] = v;
-                s_next[a * n + p] = s_cur[a * n + p] + dt * v;
+                v[a] = s_cur[(3 + a) * n + p] + dv[a] + dt * a_ext[a] + fp[a];
             }
+            or_store_node(n, p, pin[p], dt, s_cur, v, sphere, s_next);
         }
 }
 

@@ -65,6 +65,7 @@ def lib():
         "pecnn_plan_set_tiles": ([vp, i32, i32], i32),
         "pecnn_plan_get_tiles": ([vp, P(i32), P(i32)], i32),
         "pecnn_plan_set_pressure": ([vp, vp, vp], i32),
+        "pecnn_plan_set_spheres": ([vp, vp, vp], i32),
         "cloth_ms_step": ([vp, P(MsParams), vp, vp, i32, vp, vp, sz, vp], i32),
         "pecnn_theta_size": ([i32], i64),
         "pecnn_cell_theta_size": ([i32, i32], i64),
@@ -91,7 +92,8 @@ def lib():
 
 def exported_symbols():
     return ["pecnn_plan_device_bytes", "pecnn_plan_create", "pecnn_plan_destroy", "pecnn_plan_nodes",
-            "pecnn_plan_set_tiles", "pecnn_plan_get_tiles", "pecnn_plan_set_pressure", "cloth_ms_step",
+            "pecnn_plan_set_tiles", "pecnn_plan_get_tiles", "pecnn_plan_set_pressure", "pecnn_plan_set_spheres",
+            "cloth_ms_step",
             "pecnn_theta_size", "pecnn_cell_theta_size",
             "pecnn_forward", "pecnn_backward", "pecnn_rollout", "cloth_reduce_fp64", "pecnn_loss_mse",
             "pecnn_adam_step", "pecnn_gather_windows", "pecnn_workspace_bytes", "pecnn_autotune",
@@ -161,7 +163,17 @@ class Plan:
         pres = getattr(batch, "pressure", None)
         if pres is not None and np.any(np.asarray(pres) != 0):
             plan.set_pressure(pres)
+        sph = getattr(batch, "sphere", None)
+        if sph is not None and np.any(np.asarray(sph)[:, 3] > 0):
+            plan.set_spheres(sph)
         return plan
+
+    def set_spheres(self, spheres):
+        """Per-instance sphere (centre x, y, z, radius, friction) of the constraint in eq. (5)."""
+        self._s = np.ascontiguousarray(spheres, np.float32).reshape(-1)
+        if self._s.size != 5 * self.n:
+            raise ValueError("need five values per instance")
+        check(lib().pecnn_plan_set_spheres(self.handle, self._s.ctypes.data, _stream()), "pecnn_plan_set_spheres")
 
     def set_pressure(self, pressure):
         """Per-instance uniform pressure of eq. (3), N/m^2 (pecnn_plan_set_pressure)."""

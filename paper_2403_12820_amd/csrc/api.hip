@@ -273,7 +273,7 @@ int pecnn_plan_device_bytes(const pecnn_batch_desc* d, size_t* bytes) {
   std::vector<int64_t> nt;
   tile_counts(d, nt);
   *bytes = align256((size_t)d->n * sizeof(InstDev)) + kNumCfg * align256((size_t)(d->n + 1) * sizeof(int32_t)) +
-           align256((size_t)nt[kCfgChunk] * sizeof(int32_t));
+           align256((size_t)nt[kCfgChunk] * sizeof(int32_t)) + align256((size_t)d->n * kSphereStride * sizeof(float));
   return PECNN_OK;
 }
 
@@ -334,7 +334,10 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
       const int64_t chunks = ((int64_t)d->H[b] * d->W[b] + kChunk - 1) / kChunk;
       for (int64_t k = 0; k < chunks; ++k) ci[t++] = b;
     }
+    o += align256((size_t)nt[kCfgChunk] * sizeof(int32_t));
   }
+  // per-instance sphere records (all zero: no sphere)
+  const size_t sphere_off = o;
   hipStream_t st = (hipStream_t)stream;
   PECNN_HIP(hipMemcpyAsync(dev_mem, host.data(), need, hipMemcpyHostToDevice, st));
   PECNN_HIP(hipStreamSynchronize(st));
@@ -371,6 +374,7 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
     p->n_tiles[c] = (int32_t)nt[c];
   }
   p->d_chunk_inst = (int32_t*)((char*)dev_mem + chunk_off);
+  p->d_sphere = (float*)((char*)dev_mem + sphere_off);
   // defaults: wide rows for large instances, square tiles when most instances are small
   p->ms_cfg = max_hw >= 64 * 64 ? 3 : 2;
   p->cnn_cfg = max_hw >= 64 * 64 ? 0 : 2;
@@ -394,6 +398,29 @@ int pecnn_plan_destroy(pecnn_plan* p) {
   free(p->a_ext);
   free(p->pres);
   free(p);
+  return PECNN_OK;
+}
+
+int pecnn_plan_set_spheres(pecnn_plan* p, const float* sphere, void* stream) {
+  if (check_plan(p)) return PECNN_E_INVALID;
+  if (!sphere) { set_error("null sphere records"); return PECNN_E_INVALID; }
+  std::vector<float> rec((size_t)p->n * kSphereStride, 0.f);
+  int any = 0;
+  for (int b = 0; b < p->n; ++b) {
+    const float* r = sphere + 5 * (size_t)b;
+    if (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !isfinite(r[3]) || r[3] < 0.f || !(r[4] >= 0.f && r[4] <= 1.f)) {
+      set_error("instance %d: sphere centre finite, radius >= 0, friction in [0, 1]", b);
+      return PECNN_E_INVALID;
+    }
+    for (int k = 0; k < 5; ++k) rec[(size_t)b * kSphereStride + k] = r[k];
+    any |= r[3] > 0.f;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  PECNN_HIP(hipMemcpyAsync(p->d_sphere, rec.data(), rec.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  PECNN_HIP(hipStreamSynchronize(st));
+  const int ext_before = p->has_pressure || p->has_sphere;
+  p->has_sphere = any;
+  if ((p->has_pressure || p->has_sphere) != ext_before) graph_cache_free(p);
   return PECNN_OK;
 }
 
@@ -421,7 +448,8 @@ int pecnn_plan_set_pressure(pecnn_plan* p, const float* pressure, void* stream) 
   PECNN_HIP(hipMemcpyAsync(p->d_inst, hi.data(), sizeof(InstDev) * p->n, hipMemcpyHostToDevice, st));
   PECNN_HIP(hipStreamSynchronize(st));
   for (int b = 0; b < p->n; ++b) p->pres[b] = pressure[b];
-  if (any != p->has_pressure) graph_cache_free(p);  // captured chunks hold the other kernel variants
+  // captured chunks hold the kernel variants of the old setting
+  if ((any || p->has_sphere) != (p->has_pressure || p->has_sphere)) graph_cache_free(p);
   p->has_pressure = any;
   return PECNN_OK;
 }
@@ -499,6 +527,7 @@ int pecnn_backward(const pecnn_plan* p, const pecnn_model* m, const float* s_pre
   if (rc) return rc;
   if ((rc = check_model(m))) return rc;
   if (m->precision != PECNN_FP32) { set_error("backward needs an FP32 model"); return PECNN_E_UNSUPPORTED; }
+  if (p->has_sphere) { set_error("backward through the sphere constraint is not implemented"); return PECNN_E_UNSUPPORTED; }
   if (!s_prev || !s_cur || !g_next || !g_theta) { set_error("null state, gradient or theta gradient"); return PECNN_E_INVALID; }
   if (g_cur && g_prev && g_cur == g_prev) { set_error("g_cur and g_prev must differ"); return PECNN_E_INVALID; }
   const size_t need = align256(m->cell == PECNN_CELL_PAIR ? pair_backward_ws_bytes(p) : backward_ws_bytes(p, m->ch));

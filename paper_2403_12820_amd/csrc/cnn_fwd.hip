@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void cnn_fwd_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_prev, const float* __restrict__ s_cur,
     float* __restrict__ s_next, int64_t N, const float* __restrict__ theta, float dt, float alpha,
-    const int32_t* __restrict__ skip) {
+    const int32_t* __restrict__ skip, const float* __restrict__ sphere) {
   constexpr int HX = TX + 2, HY = TY + 2, PL = HX * HY;
   constexpr int MB = CH / 16, CPL = CH / 4;
   constexpr int SEGX = TX / 16, NSEG = SEGX * TY;
@@ -136,13 +136,19 @@ __global__ __launch_bounds__(256) void cnn_fwd_kernel(
           ny = __builtin_fmaf(cp, p1, ny);
           nz = __builtin_fmaf(cp, p2, nz);
         }
-        if (pin[p]) nx = ny = nz = 0.f;
+        const bool pinned = pin[p] != 0;
+        if (pinned) nx = ny = nz = 0.f;
+        float y0 = __builtin_fmaf(dt, nx, tS[base]), y1 = __builtin_fmaf(dt, ny, tS[PL + base]),
+              y2 = __builtin_fmaf(dt, nz, tS[2 * PL + base]);
+        if (!pinned)  // the constraint of eq. (5) with the instance's sphere, if it has one
+          sphere_update(sphere + b * kSphereStride, dt, tS[base], tS[PL + base], tS[2 * PL + base], nx, ny, nz, y0,
+                        y1, y2);
         s_next[3 * N + p] = nx;
         s_next[4 * N + p] = ny;
         s_next[5 * N + p] = nz;
-        s_next[0 * N + p] = __builtin_fmaf(dt, nx, tS[base]);
-        s_next[1 * N + p] = __builtin_fmaf(dt, ny, tS[PL + base]);
-        s_next[2 * N + p] = __builtin_fmaf(dt, nz, tS[2 * PL + base]);
+        s_next[0 * N + p] = y0;
+        s_next[1 * N + p] = y1;
+        s_next[2 * N + p] = y2;
       }
     }
     __syncthreads();
@@ -159,7 +165,7 @@ static void launch_cnn(const pecnn_plan* plan, int slot, const float* sp, const 
   if (grid < 8) grid = 8;
   hipLaunchKernelGGL((cnn_fwd_kernel<CH, BF, TX, TY>), dim3(grid), dim3(256), 0, st, plan->d_inst,
                      plan->d_prefix[slot], plan->n, n_tiles, plan->pin, sp, sc, sn, plan->total, theta, dt,
-                     alpha, skip);
+                     alpha, skip, plan->d_sphere);
 }
 
 template <int CH, bool BF>

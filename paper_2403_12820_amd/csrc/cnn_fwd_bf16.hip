@@ -21,13 +21,14 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // WPE: waves per SIMD the register allocation is held to (3 fits the tiles up to 256 nodes).
 // VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
 // so the halo rows load as 16-byte pieces; otherwise as single floats.
-// PRES: some instance of the batch has a pressure (eq. 3), added as a known external force.
-template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool PRES>
+// EXT: some instance of the batch has a pressure (eq. 3), added as a known external force, or a
+// sphere in the constraint of eq. (5); the others skip both uniformly.
+template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool EXT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void cnn_fwd_bf16_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_prev, const float* __restrict__ s_cur,
     float* __restrict__ s_next, int64_t N, const float* __restrict__ theta, float dt, float alpha,
-    const int32_t* __restrict__ skip) {
+    const int32_t* __restrict__ skip, const float* __restrict__ sphere) {
   constexpr int RS = TX + 8;  // LDS row stride: tile column j at 4 + j, halo columns at 3 and 4 + TX
   constexpr int HY = TY + 2;
   constexpr int PLN = HY * RS;
@@ -94,8 +95,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     return -1;
   };
   // coordinates of tile t, whose instance the cursor holds
+  int ib = 0;  // instance of the tile in I
   auto coords = [&](int t, InstDev& I, int& r0, int& c0) {
     I = tcur.I;
+    ib = tcur.b;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
@@ -220,6 +223,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 
   for (;;) {
     const InstDev Ic = I;
+    const int ibc = ib;
     const int rc0 = r0, cc0 = c0;
     // every prefetched register is consumed here on every path, so the next loads that reuse
     // them never wait on older stores
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
             float nx = (tS[3 * PLN + cell] + e0) + cx;
             float ny = (tS[4 * PLN + cell] + e1) + cy;
             float nz = (tS[5 * PLN + cell] + e2) + cz;
-            if constexpr (PRES) {
+            if constexpr (EXT) {
               if (Ic.pres != 0.f) {  // eq. (3) at S^k, uniform over the workgroup
                 const int nb[4] = {1, RS, -1, -RS};  // right, down, left, up
                 float d[4][3];
@@ -350,13 +354,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
                 nz = __builtin_fmaf(cp, p2, nz);
               }
             }
-            if (tP[sy * TX + sx]) nx = ny = nz = 0.f;
+            const bool pinned = tP[sy * TX + sx] != 0;
+            if (pinned) nx = ny = nz = 0.f;
+            float y0, y1, y2;
+            if constexpr (EXT) {
+              if (!pinned) {
+                sphere_update(sphere + ibc * kSphereStride, dt, tS[cell], tS[PLN + cell], tS[2 * PLN + cell], nx, ny,
+                              nz, y0, y1, y2);
+              } else {
+                y0 = tS[cell];
+                y1 = tS[PLN + cell];
+                y2 = tS[2 * PLN + cell];
+              }
+            } else {
+              y0 = __builtin_fmaf(dt, nx, tS[cell]);
+              y1 = __builtin_fmaf(dt, ny, tS[PLN + cell]);
+              y2 = __builtin_fmaf(dt, nz, tS[2 * PLN + cell]);
+            }
             gst(s_next, 3 * N32 + p, nx);
             gst(s_next, 4 * N32 + p, ny);
             gst(s_next, 5 * N32 + p, nz);
-            gst(s_next, p, __builtin_fmaf(dt, nx, tS[cell]));
-            gst(s_next, N32 + p, __builtin_fmaf(dt, ny, tS[PLN + cell]));
-            gst(s_next, 2 * N32 + p, __builtin_fmaf(dt, nz, tS[2 * PLN + cell]));
+            gst(s_next, p, y0);
+            gst(s_next, N32 + p, y1);
+            gst(s_next, 2 * N32 + p, y2);
           }
         }
       }
@@ -367,14 +387,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool PRES>
+template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool EXT>
 static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const float* sc, float* sn,
                         const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
   const int n_tiles = plan->n_tiles[slot];
   static int per_cu = 0;  // resident workgroups per CU of this instantiation
   if (per_cu == 0) {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC, PRES>, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC, EXT>, 256, 0) !=
             hipSuccess ||
         v < 1)
       v = 2;
@@ -384,20 +404,20 @@ static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const
   const int need = ((n_tiles + 7) / 8) * 8;
   if (need < grid) grid = need;
   if (grid < 8) grid = 8;
-  hipLaunchKernelGGL((cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC, PRES>), dim3(grid), dim3(256), 0, st, plan->d_inst,
+  hipLaunchKernelGGL((cnn_fwd_bf16_kernel<CH, TX, TY, A1, WPE, VEC, EXT>), dim3(grid), dim3(256), 0, st, plan->d_inst,
                      plan->d_prefix[slot], plan->n, n_tiles, plan->pin, sp, sc, sn, plan->total, theta, dt, alpha,
-                     skip);
+                     skip, plan->d_sphere);
 }
 
-template <int CH, bool A1, bool VEC, bool PRES>
+template <int CH, bool A1, bool VEC, bool EXT>
 static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                       const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
   const int slot = cnn_cfg_slot(cfg);
   switch (cfg) {
-    case 0: launch_bf16<CH, 64, 4, A1, 3, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 1: launch_bf16<CH, 32, 8, A1, 3, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 2: launch_bf16<CH, 16, 16, A1, 3, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
-    case 3: launch_bf16<CH, 64, 8, A1, 2, VEC, PRES>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 0: launch_bf16<CH, 64, 4, A1, 3, VEC, EXT>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 1: launch_bf16<CH, 32, 8, A1, 3, VEC, EXT>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 2: launch_bf16<CH, 16, 16, A1, 3, VEC, EXT>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
+    case 3: launch_bf16<CH, 64, 8, A1, 2, VEC, EXT>(plan, slot, sp, sc, sn, theta, dt, alpha, skip, st); break;
     default: return PECNN_E_INVALID;
   }
   return PECNN_OK;
@@ -406,7 +426,7 @@ static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const fl
 template <int CH, bool A1>
 static int bf16_cfg(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                     const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
-  if (plan->has_pressure)
+  if (plan->has_pressure || plan->has_sphere)
     return plan->vec4 ? bf16_cfg_v<CH, A1, true, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)
                       : bf16_cfg_v<CH, A1, false, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
   return plan->vec4 ? bf16_cfg_v<CH, A1, true, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)

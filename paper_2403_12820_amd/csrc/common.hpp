@@ -167,6 +167,43 @@ __device__ __forceinline__ void pressure_adjoint_gather(int H, int W, int64_t of
   }
 }
 
+// Per-instance sphere record in the plan: centre x, y, z, radius (0: none), friction, padding.
+constexpr int kSphereStride = 8;
+
+// Position update of eq. (5) for a free node, x' = x + dt v', with the constraint operator
+// extended by a sphere (cloth-object collision by intersection elimination, section 3.1): when
+// x + dt v lies inside the sphere (|y - c| < R) the node moves to the nearest surface point
+// c + R n, n = (y - c)/|y - c|, its inward normal velocity is removed and its tangential velocity
+// is scaled by 1 - friction. sph: the instance's record; v is in/out.
+__device__ __forceinline__ void sphere_update(const float* __restrict__ sph, float dt, float x0, float x1, float x2,
+                                              float& v0, float& v1, float& v2, float& y0, float& y1, float& y2) {
+  y0 = __builtin_fmaf(dt, v0, x0);
+  y1 = __builtin_fmaf(dt, v1, x1);
+  y2 = __builtin_fmaf(dt, v2, x2);
+  const float R = sph[3];
+  if (R > 0.f) {
+    const float d0 = y0 - sph[0], d1 = y1 - sph[1], d2 = y2 - sph[2];
+    const float r2 = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
+    if (r2 < R * R) {
+      float n0 = 0.f, n1 = 0.f, n2 = 1.f;
+      if (r2 > 0.f) {
+        const float ir = 1.f / __builtin_sqrtf(r2);
+        n0 = d0 * ir;
+        n1 = d1 * ir;
+        n2 = d2 * ir;
+      }
+      const float vn = __builtin_fmaf(v2, n2, __builtin_fmaf(v1, n1, v0 * n0));
+      const float k = 1.f - sph[4], vp = vn > 0.f ? vn : 0.f;
+      v0 = __builtin_fmaf(k, v0 - vn * n0, vp * n0);
+      v1 = __builtin_fmaf(k, v1 - vn * n1, vp * n1);
+      v2 = __builtin_fmaf(k, v2 - vn * n2, vp * n2);
+      y0 = __builtin_fmaf(R, n0, sph[0]);
+      y1 = __builtin_fmaf(R, n1, sph[1]);
+      y2 = __builtin_fmaf(R, n2, sph[2]);
+    }
+  }
+}
+
 struct MsParamsDev {
   float k[3];     // spring constants per family
   float mu, drag;
@@ -197,6 +234,8 @@ struct pecnn_plan {
   int32_t vec4;                         // every row of every plane starts 16-byte aligned
   float* pres;                          // host copy of the per-instance pressure (eq. 3)
   int32_t has_pressure;                 // some instance has a non-zero pressure
+  float* d_sphere;                      // device: per-instance sphere records (kSphereStride floats)
+  int32_t has_sphere;                   // some instance has a sphere
   void* graph_cache;                    // rollout graph cache (host object)
 };
 

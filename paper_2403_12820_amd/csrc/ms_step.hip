@@ -20,7 +20,8 @@ __device__ constexpr Spring kSprings[12] = {
 
 // VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
 // so the tile rows load as 16-byte pieces; otherwise as single floats.
-// PRES: some instance of the batch has a pressure (eq. 3); the others skip it uniformly.
+// EXT: some instance of the batch has a pressure (eq. 3) or a sphere in its constraint; the
+// others skip both uniformly.
 // PAIR: instead of the springs, one frame of the paper's own cell read literally (section 3.2):
 // twelve channels, one per stencil neighbour j, phi_c = s_c (x_j - x), xi_c = s_c (v_j - v) with
 // the same frozen two-point filter on each axis (eq. 6; zero when j is off the grid), then per axis
@@ -32,11 +33,11 @@ struct PairArgs {
   const int32_t* skip;   // instances to leave alone (fallen back), or null
 };
 
-template <int TX, int TY, int RY, bool VEC, bool PRES, bool PAIR = false>
+template <int TX, int TY, int RY, bool VEC, bool EXT, bool PAIR = false>
 __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_in, float* __restrict__ s_out,
-    int64_t N, MsParamsDev P, const uint8_t* __restrict__ active, PairArgs pa) {
+    int64_t N, MsParamsDev P, const uint8_t* __restrict__ active, PairArgs pa, const float* __restrict__ sphere) {
   constexpr int NT = TX * (TY / RY);
   constexpr int RS = TX + 8;  // LDS row stride: tile column j at 4 + j, halo columns 2, 3 and 4+TX, 5+TX
   constexpr int HY = TY + 4;
@@ -80,8 +81,10 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     return -1;
   };
   // coordinates of tile t, whose instance the cursor holds
+  int ib = 0;  // instance of the tile in I
   auto coords = [&](int t, InstDev& I, int& r0, int& c0) {
     I = tcur.I;
+    ib = tcur.b;
     const int lt = t - tcur.start;
     const int tiles_x = (I.W + TX - 1) / TX;
     r0 = (lt / tiles_x) * TY;
@@ -166,6 +169,7 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
 
   for (;;) {
     const InstDev Ic = I;
+    const int ibc = ib;
     const int rc0 = r0, cc0 = c0;
     // every prefetched register is consumed here on every path, so the next loads that reuse
     // them never wait on older stores
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
               n0 = (v0 + acc[0]) + pa.dt * Ic.ax;
               n1 = (v1 + acc[1]) + pa.dt * Ic.ay;
               n2 = (v2 + acc[2]) + pa.dt * Ic.az;
-              if constexpr (PRES) {
+              if constexpr (EXT) {
                 if (Ic.pres != 0.f) {  // eq. (3) at S^k, a known external force
                   const int nb[4] = {1, RS, -1, -RS};  // right, down, left, up
                   float d[4][3];
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
               f1 = __builtin_fmaf(cf, d1, f1);
               f2 = __builtin_fmaf(cf, d2, f2);
             }
-            if constexpr (PRES) {
+            if constexpr (EXT) {
               if (Ic.pres != 0.f) {  // eq. (3), uniform over the workgroup
                 const int nb[4] = {1, RS, -1, -RS};  // right, down, left, up
                 float d[4][3];
@@ -283,12 +287,26 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
           }
           const int N32 = (int)N;
           const float dto = PAIR ? pa.dt : P.dt;
+          float y0, y1, y2;
+          if constexpr (EXT) {
+            if (!tP[ly * TX + tx]) {
+              sphere_update(sphere + ibc * kSphereStride, dto, x0, x1, x2, n0, n1, n2, y0, y1, y2);
+            } else {
+              y0 = __builtin_fmaf(dto, n0, x0);
+              y1 = __builtin_fmaf(dto, n1, x1);
+              y2 = __builtin_fmaf(dto, n2, x2);
+            }
+          } else {
+            y0 = __builtin_fmaf(dto, n0, x0);
+            y1 = __builtin_fmaf(dto, n1, x1);
+            y2 = __builtin_fmaf(dto, n2, x2);
+          }
           gst(s_out, 3 * N32 + p, n0);
           gst(s_out, 4 * N32 + p, n1);
           gst(s_out, 5 * N32 + p, n2);
-          gst(s_out, p, __builtin_fmaf(dto, n0, x0));
-          gst(s_out, N32 + p, __builtin_fmaf(dto, n1, x1));
-          gst(s_out, 2 * N32 + p, __builtin_fmaf(dto, n2, x2));
+          gst(s_out, p, y0);
+          gst(s_out, N32 + p, y1);
+          gst(s_out, 2 * N32 + p, y2);
         }
       }
     }
@@ -313,9 +331,9 @@ static void launch_ms(const pecnn_plan* plan, int slot, const MsParamsDev& P, co
   const int grid = grid_for(n_tiles, 8);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TX * (TY / RY)), 0, st, plan->d_inst, plan->d_prefix[slot], plan->n,
-                       n_tiles, plan->pin, in, out, plan->total, P, active, PairArgs{});
+                       n_tiles, plan->pin, in, out, plan->total, P, active, PairArgs{}, plan->d_sphere);
   };
-  if (plan->has_pressure) {
+  if (plan->has_pressure || plan->has_sphere) {
     if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, true>);
     else go(ms_step_kernel<TX, TY, RY, false, true>);
   } else {
@@ -332,9 +350,9 @@ static void launch_pair(const pecnn_plan* plan, int slot, const PairArgs& pa, co
   const MsParamsDev P{};
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TX * (TY / RY)), 0, st, plan->d_inst, plan->d_prefix[slot], plan->n,
-                       n_tiles, plan->pin, in, out, plan->total, P, (const uint8_t*)nullptr, pa);
+                       n_tiles, plan->pin, in, out, plan->total, P, (const uint8_t*)nullptr, pa, plan->d_sphere);
   };
-  if (plan->has_pressure) {
+  if (plan->has_pressure || plan->has_sphere) {
     if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, true, true>);
     else go(ms_step_kernel<TX, TY, RY, false, true, true>);
   } else {

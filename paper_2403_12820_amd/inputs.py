@@ -189,6 +189,7 @@ class Batch:
     state: np.ndarray           # float32 [6, N_total]
     node_off: np.ndarray = field(default=None)  # int64 [n+1]
     pressure: np.ndarray = field(default=None)  # float32 [n], eq. (3)
+    sphere: np.ndarray = field(default=None)    # float32 [n, 5]: centre, radius (0: none), friction
 
     @property
     def n(self) -> int:
