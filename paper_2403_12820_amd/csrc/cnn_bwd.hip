@@ -59,18 +59,27 @@ __device__ __forceinline__ bool chunk_node(const InstDev* inst, const int32_t* p
   return local < inst[b].H * inst[b].W;
 }
 
+// theta in LDS for the node kernel: the conv block transposed to KT[t][c] (channel fastest), so
+// that the per-tap loops read four channels per 16-byte LDS access; the other blocks as in theta.
+template <int CH>
+struct NodeTheta {
+  static constexpr int KT = 0, A = 54 * CH, B = A + CH * CH, WL = B + CH * CH, WN = WL + 3 * CH, WD = WN + 3 * CH,
+                       P = WD + 3 * CH + 3;
+};
+
 template <int CH>
 __global__ __launch_bounds__(256) void bwd_node_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_prev, const float* __restrict__ s_cur,
     const float* __restrict__ g_next, int64_t N, const float* __restrict__ theta, float dt, float alpha,
     float* __restrict__ fac) {
-  constexpr int P = CH * 54 + 2 * CH * CH + 9 * CH + 3;
-  constexpr int oA = CH * 54, oB = oA + CH * CH, oWL = oB + CH * CH, oWN = oWL + 3 * CH, oWD = oWN + 3 * CH;
-  constexpr int SW = 2 * CH + 1;  // per-thread scratch row (odd stride: no bank conflicts)
-  __shared__ float th[P];
-  __shared__ float scr[256 * SW];
-  for (int e = threadIdx.x; e < P; e += 256) th[e] = theta[e];
+  using T = NodeTheta<CH>;
+  __shared__ __align__(16) float th[T::P];
+  for (int e = threadIdx.x; e < 54 * CH; e += 256) {
+    const int t = e / CH, c = e - (e / CH) * CH;
+    th[e] = theta[c * 54 + t];
+  }
+  for (int e = 54 * CH + threadIdx.x; e < T::P; e += 256) th[e] = theta[e];
   __syncthreads();
 
   int b;
@@ -81,7 +90,7 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
   const int64_t p = I.off + local;
   const BwdLayout L = bwd_layout(CH);
   float* __restrict__ F = fac + fac_node(p, L.rows);  // feature row r of node p lives at F[r * 32]
-  float* __restrict__ my = scr + threadIdx.x * SW;
+  auto th4 = [&](int e) { return *reinterpret_cast<const float4*>(&th[e]); };
 
   // forward recompute: phi = K U(S^k), xi = K U(S^k - S^{k-1}); im2col entries go to the table
   float phi[CH], xi[CH];
@@ -104,27 +113,41 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
       F[(L.uk + t) * 32] = uk;
       F[(L.ud + t) * 32] = ud;
 #pragma unroll
-      for (int r = 0; r < CH; ++r) {
-        phi[r] = __builtin_fmaf(th[r * 54 + t], uk, phi[r]);
-        xi[r] = __builtin_fmaf(th[r * 54 + t], ud, xi[r]);
+      for (int r = 0; r < CH; r += 4) {
+        const float4 w = th4(T::KT + t * CH + r);
+        phi[r] = __builtin_fmaf(w.x, uk, phi[r]);
+        phi[r + 1] = __builtin_fmaf(w.y, uk, phi[r + 1]);
+        phi[r + 2] = __builtin_fmaf(w.z, uk, phi[r + 2]);
+        phi[r + 3] = __builtin_fmaf(w.w, uk, phi[r + 3]);
+        xi[r] = __builtin_fmaf(w.x, ud, xi[r]);
+        xi[r + 1] = __builtin_fmaf(w.y, ud, xi[r + 1]);
+        xi[r + 2] = __builtin_fmaf(w.z, ud, xi[r + 2]);
+        xi[r + 3] = __builtin_fmaf(w.w, ud, xi[r + 3]);
       }
     }
   }
-  // the two Ch x Ch maps of the nonlinear branch
-#pragma unroll
-  for (int c = 0; c < CH; ++c) my[c] = phi[c];
+  // the two Ch x Ch maps of the nonlinear branch: a = A phi, bb = B phi (rows read along c)
   float a[CH], bb[CH];
 #pragma unroll
-  for (int r = 0; r < CH; ++r) { a[r] = 0.f; bb[r] = 0.f; }
-#pragma unroll 1
-  for (int c = 0; c < CH; ++c) {
-    const float pc = my[c];
+  for (int r = 0; r < CH; ++r) {
+    float sa = 0.f, sb = 0.f;
 #pragma unroll
-    for (int r = 0; r < CH; ++r) {
-      a[r] = __builtin_fmaf(th[oA + r * CH + c], pc, a[r]);
-      bb[r] = __builtin_fmaf(th[oB + r * CH + c], pc, bb[r]);
+    for (int c = 0; c < CH; c += 4) {
+      const float4 wa = th4(T::A + r * CH + c), wb = th4(T::B + r * CH + c);
+      sa = __builtin_fmaf(wa.x, phi[c], sa);
+      sa = __builtin_fmaf(wa.y, phi[c + 1], sa);
+      sa = __builtin_fmaf(wa.z, phi[c + 2], sa);
+      sa = __builtin_fmaf(wa.w, phi[c + 3], sa);
+      sb = __builtin_fmaf(wb.x, phi[c], sb);
+      sb = __builtin_fmaf(wb.y, phi[c + 1], sb);
+      sb = __builtin_fmaf(wb.z, phi[c + 2], sb);
+      sb = __builtin_fmaf(wb.w, phi[c + 3], sb);
     }
+    a[r] = sa;
+    bb[r] = sb;
   }
+  // compiler fence: the weight reads below are issued again rather than kept live from above
+  asm volatile("" ::: "memory");
   // adjoint of eq. (5)
   float gdv[3];
   const bool pinned = pin[p] != 0;
@@ -134,8 +157,8 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
     gdv[k] = pinned ? 0.f : gvt;
     F[(L.gdv + k) * 32] = gdv[k];
   }
-  // heads and ISRU branches; afterwards phi holds the head/derivative part of dLoss/dphi,
-  // xi holds dLoss/dxi, and my[] holds the adjoints of (A phi) and (B phi)
+  // heads and ISRU branches; afterwards phi holds the head/derivative part of dLoss/dphi, xi holds
+  // dLoss/dxi, and a, bb hold the adjoints of (A phi) and (B phi)
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const float r1 = __builtin_amdgcn_rsqf(1.f + alpha * phi[c] * phi[c]);
@@ -144,9 +167,9 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
     const float r2 = __builtin_amdgcn_rsqf(1.f + alpha * z * z);
     const float nn = z * r2, dnn = r2 * r2 * r2;
     const float dd = xi[c] * gs;
-    const float gphi_h = th[oWL + c] * gdv[0] + th[oWL + CH + c] * gdv[1] + th[oWL + 2 * CH + c] * gdv[2];
-    const float gnn = th[oWN + c] * gdv[0] + th[oWN + CH + c] * gdv[1] + th[oWN + 2 * CH + c] * gdv[2];
-    const float gdd = th[oWD + c] * gdv[0] + th[oWD + CH + c] * gdv[1] + th[oWD + 2 * CH + c] * gdv[2];
+    const float gphi_h = th[T::WL + c] * gdv[0] + th[T::WL + CH + c] * gdv[1] + th[T::WL + 2 * CH + c] * gdv[2];
+    const float gnn = th[T::WN + c] * gdv[0] + th[T::WN + CH + c] * gdv[1] + th[T::WN + 2 * CH + c] * gdv[2];
+    const float gdd = th[T::WD + c] * gdv[0] + th[T::WD + CH + c] * gdv[1] + th[T::WD + 2 * CH + c] * gdv[2];
     const float gz = gnn * dnn;
     const float ga = gz * bb[c], gb = gz * a[c];
     F[(L.phi + c) * 32] = phi[c];
@@ -154,17 +177,25 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
     F[(L.dd + c) * 32] = dd;
     F[(L.ga + c) * 32] = ga;
     F[(L.gb + c) * 32] = gb;
-    my[c] = ga;
-    my[CH + c] = gb;
+    a[c] = ga;
+    bb[c] = gb;
     phi[c] = gphi_h + gdd * xi[c] * dgs;
     xi[c] = gdd * gs;
     F[(L.gxi + c) * 32] = xi[c];
   }
-#pragma unroll 1
-  for (int r = 0; r < CH; ++r) {
-    const float gar = my[r], gbr = my[CH + r];
+  asm volatile("" ::: "memory");
+  // dLoss/dphi += A^T ga + B^T gb (rows of A and B read along c)
 #pragma unroll
-    for (int c = 0; c < CH; ++c) phi[c] = __builtin_fmaf(th[oB + r * CH + c], gbr, __builtin_fmaf(th[oA + r * CH + c], gar, phi[c]));
+  for (int r = 0; r < CH; ++r) {
+    const float gar = a[r], gbr = bb[r];
+#pragma unroll
+    for (int c = 0; c < CH; c += 4) {
+      const float4 wa = th4(T::A + r * CH + c), wb = th4(T::B + r * CH + c);
+      phi[c] = __builtin_fmaf(wb.x, gbr, __builtin_fmaf(wa.x, gar, phi[c]));
+      phi[c + 1] = __builtin_fmaf(wb.y, gbr, __builtin_fmaf(wa.y, gar, phi[c + 1]));
+      phi[c + 2] = __builtin_fmaf(wb.z, gbr, __builtin_fmaf(wa.z, gar, phi[c + 2]));
+      phi[c + 3] = __builtin_fmaf(wb.w, gbr, __builtin_fmaf(wa.w, gar, phi[c + 3]));
+    }
   }
 #pragma unroll
   for (int c = 0; c < CH; ++c) F[(L.gphi + c) * 32] = phi[c];
@@ -173,9 +204,16 @@ __global__ __launch_bounds__(256) void bwd_node_kernel(
   for (int t = 0; t < 54; ++t) {
     float gk = 0.f, gd = 0.f;
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      gk = __builtin_fmaf(th[c * 54 + t], phi[c], gk);
-      gd = __builtin_fmaf(th[c * 54 + t], xi[c], gd);
+    for (int c = 0; c < CH; c += 4) {
+      const float4 w = th4(T::KT + t * CH + c);
+      gk = __builtin_fmaf(w.x, phi[c], gk);
+      gk = __builtin_fmaf(w.y, phi[c + 1], gk);
+      gk = __builtin_fmaf(w.z, phi[c + 2], gk);
+      gk = __builtin_fmaf(w.w, phi[c + 3], gk);
+      gd = __builtin_fmaf(w.x, xi[c], gd);
+      gd = __builtin_fmaf(w.y, xi[c + 1], gd);
+      gd = __builtin_fmaf(w.z, xi[c + 2], gd);
+      gd = __builtin_fmaf(w.w, xi[c + 3], gd);
     }
     F[(L.gus + t) * 32] = gk + gd;
     F[(L.gud + t) * 32] = gd;
