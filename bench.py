@@ -70,11 +70,12 @@ def load_theta(ch, cell="conv"):
     return I.init_theta(ch, seed=1), "random N(0, 0.02) seed 1"
 
 
-def cpu_baseline(ch, theta, budget_s=10.0, cell="conv"):
-    """The FP64 oracle's CNN frame on one 256 x 256 cloth, repeated for about budget_s seconds."""
+def _oracle_frames(args):
+    """One worker: FP64 oracle frames of one 256 x 256 cloth (seeded per worker) for budget_s."""
+    ch, theta, budget_s, cell, seed = args
     import oracle
     from paper_2403_12820_amd import inputs as I
-    sc = I.random_scenes([(256, 256)], seed=5)[0]
+    sc = I.random_scenes([(256, 256)], seed=seed)[0]
     s = sc.state.astype(np.float64)
     th = theta.astype(np.float64)
     t0 = time.perf_counter()
@@ -89,10 +90,27 @@ def cpu_baseline(ch, theta, budget_s=10.0, cell="conv"):
         frames += 1
         if time.perf_counter() - t0 >= budget_s:
             break
-    dt = time.perf_counter() - t0
-    return {"value": frames * 256 * 256 / dt, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d FP64 %s frames of one 256x256 cloth, single thread, %.1f s" % (
-                frames, "pair-cell" if cell == "pair" else "CNN (Ch=%d)" % ch, dt)}
+    return frames, time.perf_counter() - t0
+
+
+def cpu_baseline(ch, theta, budget_s=10.0, cell="conv", cores=1, stride=10):
+    """The FP64 oracle's frame on 256 x 256 cloths for about budget_s seconds, on `cores` worker
+    processes (one cloth each), counted like `value`: nodes x frames x stride / time. Runs before
+    the GPU is touched, so the workers are plain forks."""
+    work = [(ch, theta, budget_s, cell, 5 + k) for k in range(cores)]
+    if cores == 1:
+        res = [_oracle_frames(work[0])]
+    else:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(cores) as pool:
+            res = pool.map(_oracle_frames, work)
+    frames = sum(f for f, _ in res)
+    rate = sum(f * 256 * 256 * stride / t for f, t in res)
+    what = "pair-cell" if cell == "pair" else "CNN (Ch=%d)" % ch
+    return {"value": rate, "unit": "node-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "%d FP64 %s frames of 256x256 cloths (one per worker), %d worker process%s, %.1f s each; "
+                      "counted like value: nodes x frames x %d simulator steps / time" % (
+                          frames, what, cores, "" if cores == 1 else "es", max(t for _, t in res), stride)}
 
 
 def main():
@@ -112,6 +130,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-cores", type=int, default=1, help="worker processes for the oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cell", choices=("conv", "pair"), default="conv",
                     help="conv: the bf16 convolution cell (default); pair: the paper's own cell, FP32")
@@ -120,6 +139,12 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (instances would shard "
               "across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
+
+    pair = args.cell == "pair"
+    ch = 12 if pair else args.ch
+    theta_np, theta_kind = load_theta(ch, args.cell)
+    # the CPU baseline first, before anything touches the GPU
+    cpu = None if args.no_cpu else cpu_baseline(ch, theta_np, args.cpu_seconds, args.cell, args.cpu_cores)
 
     import torch
     from paper_2403_12820_amd import _lib as L
@@ -141,9 +166,6 @@ def main():
     batch = I.make_batch(scenes)
     N = batch.total
     plan = L.Plan.from_batch(batch, dev)
-    pair = args.cell == "pair"
-    ch = 12 if pair else args.ch
-    theta_np, theta_kind = load_theta(ch, args.cell)
     theta = torch.tensor(theta_np, device=dev)
     if pair:
         model = L.make_model(theta, 12, L.PECNN_FP32, dt=dt_nn, cell=L.CELL_PAIR)
@@ -258,8 +280,8 @@ def main():
                                 "cnn_fwd_bf16_kernel<32, %s>" % CNN_TILES.get(cnn_cfg, "?")),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(ch, theta_np, args.cpu_seconds, args.cell)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     plan.close()
     print(json.dumps(out))
 
