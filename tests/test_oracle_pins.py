@@ -48,7 +48,7 @@ def _spring_counts_by_energy(H, W):
 
 
 def test_p1_spring_count_matches_paper():
-    """Section 4.1: 100 x 100 mass points form around 60k springs."""
+    """Section 4.1 prints about 60 thousand springs for 100 x 100 mass points."""
     rows = [l.split() for l in open(os.path.join(GOLDEN, "spring_count_100x100.txt")) if l.strip() and l[0] != "#"]
     H, W, printed, tol = int(rows[0][0]), int(rows[0][1]), float(rows[0][2]), float(rows[0][3])
     c = _spring_counts_by_energy(H, W)
