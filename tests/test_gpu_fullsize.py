@@ -176,3 +176,61 @@ def test_training_trajectories_full_size():
             got = tr.frames[f][:, sl].cpu().numpy().astype(np.float64)
             ref = oracle.ms_run(128, 128, sc.h, sc.mass, sc.a_ext, sc.pin, sc.state.astype(np.float64), MAT, 10 * f)
             assert np.abs(got[:3] - ref[:3]).max() <= 1e-5 * width, (b, f)
+
+
+def test_bench_size_with_pressure_spheres_and_pair_cell():
+    """128 cloths of 256 x 256 with a pressure on some instances and a ball under others, so the
+    frames run their pressure-and-sphere kernel variants at full size: the bf16 frame (autotuned
+    tiles) and the pair-cell frame on sampled instances against the oracle."""
+    import torch
+    from paper_2403_12820_amd import _lib as L
+    batch = I.make_batch(I.random_scenes([(256, 256)] * 128, seed=5))
+    s1 = batch.state.astype(np.float64)
+    s1[3:] = I.random_array((3, batch.total), seed=71, scale=0.05)
+    s0 = s1.copy()
+    s0[:3] -= 5e-3 * s1[3:]
+    batch.state = s1.astype(np.float32)
+    side = 255 * float(batch.h[0])
+    batch.pressure = np.array([3.0 if b % 3 == 1 else 0.0 for b in range(batch.n)], np.float32)
+    batch.sphere = np.array([[side / 2, side / 2, -1.98, 2.0, 0.5] if b % 3 == 2 else [0, 0, 0, 0, 0]
+                             for b in range(batch.n)], np.float32)
+    plan = L.Plan.from_batch(batch)
+    th = (I.init_theta(32, seed=1).astype(np.float64) * 20).astype(np.float32)
+    model = L.make_model(dev_tensor(th), 32, L.PECNN_BF16, dt=5e-3)
+    a, b, c = dev_tensor(s0), dev_tensor(s1), torch.zeros(6, batch.total, device="cuda")
+    L.pecnn_autotune(plan, L.ms_params(MAT), model, a.clone(), b.clone(), c, reps=3)
+    out = torch.zeros(6, batch.total, device="cuda")
+    L.pecnn_forward(plan, model, dev_tensor(s0.astype(np.float32)), dev_tensor(s1.astype(np.float32)), out)
+    pth = I.init_pair_theta(seed=3)
+    pmodel = L.make_model(dev_tensor(pth), 12, L.PECNN_FP32, dt=5e-3, cell=L.CELL_PAIR)
+    pout = torch.zeros(6, batch.total, device="cuda")
+    L.pecnn_forward(plan, pmodel, b, b, pout)
+    torch.cuda.synchronize()
+    got, pgot = out.cpu().numpy().astype(np.float64), pout.cpu().numpy().astype(np.float64)
+    s0f, s1f = s0.astype(np.float32).astype(np.float64), s1.astype(np.float32).astype(np.float64)
+    def decided(free, sph, margin):
+        # nodes whose unconstrained update lies within `margin` of the sphere are decided in FP32
+        # on the GPU and in FP64 here, possibly differently: they are left out
+        if sph is None:
+            return np.ones(free.shape[1], bool)
+        r = np.linalg.norm(free[:3] - sph[:3, None].astype(np.float64), axis=0)
+        return np.abs(r - sph[3]) > margin * sph[3]
+
+    for k in (1, 2, 64):  # pressure, ball, plain
+        sl = batch.instance(k)
+        pm = float(batch.pressure[k]) / float(batch.mass[k])
+        sph = batch.sphere[k] if batch.sphere[k, 3] > 0 else None
+        args = (256, 256, 32, 1.0, 5e-3, batch.a_ext[k].astype(np.float64), batch.pin[sl], th.astype(np.float64),
+                s0f[:, sl], s1f[:, sl])
+        em, _ = oracle.cnn_forward(*args, emu=7, pm=pm, sphere=sph)
+        ok = decided(oracle.cnn_forward(*args, emu=7, pm=pm)[0], sph, 2e-5)  # bf16 moves y by ~1e-6 m
+        assert ok.sum() >= ok.size - 10, k
+        assert rel_inf(got[3:, sl][:, ok], em[3:, ok]) <= 2.0 ** -8, k
+        assert np.abs(got[:3, sl][:, ok] - em[:3, ok]).max() <= 1e-4, k
+        pargs = (256, 256, 1.0, 5e-3, batch.a_ext[k].astype(np.float64), batch.pin[sl], pth.astype(np.float64),
+                 s1f[:, sl])
+        pr, _ = oracle.pair_forward(*pargs, pm=pm, sphere=sph)
+        ok = decided(oracle.pair_forward(*pargs, pm=pm)[0], sph, 1e-5)
+        assert ok.sum() >= ok.size - 5, k
+        assert rel_inf(pgot[3:, sl][:, ok], pr[3:, ok]) <= 1e-5, k
+        assert np.abs(pgot[:3, sl][:, ok] - pr[:3, ok]).max() <= 1e-5 * side, k
