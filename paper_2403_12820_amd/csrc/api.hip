@@ -689,7 +689,10 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
       PECNN_HIP(hipStreamBeginCapture(gc->capture, hipStreamCaptureModeThreadLocal));
       rc = record_chunk(p, m, sim, g, buf, w.T, len, with_ms, guard_on, fallback, stats_d, w, gc->capture);
       hipError_t e2 = hipStreamEndCapture(gc->capture, &graph);
-      if (rc) return rc;
+      if (rc) {
+        if (e2 == hipSuccess) (void)hipGraphDestroy(graph);
+        return rc;
+      }
       if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
       hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);

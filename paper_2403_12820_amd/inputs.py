@@ -42,6 +42,9 @@ def _mix64_int(z: int) -> int:
     return z ^ (z >> 31)
 
 
+_CHUNK = 1 << 20
+
+
 class Stream:
     """Counter-based splitmix64 stream: value n is mix64(base + (n+1)*gamma)."""
 
@@ -58,12 +61,20 @@ class Stream:
 
     def uniform(self, n: int) -> np.ndarray:
         """Doubles in [0, 1) from the top 53 bits."""
-        return (self.u64(n) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+        out = np.empty(n, np.float64)
+        for a in range(0, n, _CHUNK):  # in cache-sized pieces: same values, far fewer page faults
+            m = min(_CHUNK, n - a)
+            out[a:a + m] = (self.u64(m) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+        return out
 
     def normal(self, n: int) -> np.ndarray:
         """Standard normals by Box-Muller, one pair of uniforms per value (cosine branch)."""
-        u = self.uniform(2 * n).reshape(n, 2)
-        return np.sqrt(-2.0 * np.log1p(-u[:, 0])) * np.cos(2.0 * math.pi * u[:, 1])
+        out = np.empty(n, np.float64)
+        for a in range(0, n, _CHUNK):
+            m = min(_CHUNK, n - a)
+            u = self.uniform(2 * m).reshape(m, 2)
+            out[a:a + m] = np.sqrt(-2.0 * np.log1p(-u[:, 0])) * np.cos(2.0 * math.pi * u[:, 1])
+        return out
 
 
 # --------------------------------------------------------------------------- material
