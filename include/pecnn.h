@@ -15,7 +15,7 @@
  * Ownership: the caller allocates and frees every buffer (state, gradients, parameters,
  * workspaces, plan memory). The library never allocates device memory. Host memory is
  * allocated only for plan handles (pecnn_plan_create / pecnn_plan_destroy) and the
- * rollout's graph cache inside a plan.
+ * rollout's graph cache inside a plan (its graphs, a capture stream and one pinned int).
  *
  * Errors: every entry point validates its arguments before any launch and returns a
  * negative pecnn_status with no side effect on invalid input. A failed HIP call returns
@@ -195,8 +195,9 @@ typedef struct {
    FP64 [n][4] or NULL: energy at the start, energy at the last check, largest structural
    stretch seen at checks, network step of the fall-back (-1 if none).
    ws: pecnn_workspace_bytes(plan, model, PECNN_WS_ROLLOUT). The steps between checks run as
-   one captured HIP graph (cached in the plan per buffer set); the host reads the fallback
-   count once per check. */
+   one captured HIP graph (cached in the plan per buffer set). The host reads the fallback
+   count at the start and after every check but the last, so the call synchronises 'stream'
+   that often; it returns with the last graph still queued. */
 int pecnn_rollout(pecnn_plan* plan, const pecnn_model* model, const cloth_ms_params* sim,
                   const pecnn_guard* guard, float* s_prev, float* s_cur, int32_t n_steps,
                   int32_t* fallback, double* stats, void* ws, size_t ws_bytes, void* stream);
