@@ -1,7 +1,7 @@
 // FP64 diagnostics (position error, energy, stretch ratio), the data term of the loss (eq. 8),
 // Adam (Table 1) and the training-window gather. Reductions are two-stage with a fixed order
-// (per-chunk tree in LDS, then per-instance or global sums in index order): bitwise
-// reproducible run to run.
+// (per-chunk sums across lanes and waves, then per-instance or global sums in index order):
+// bitwise reproducible run to run.
 #include "common.hpp"
 
 namespace pecnn {
@@ -34,58 +34,84 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void reduce_chunk_kernel(
+// Wave-level reductions in a fixed order (an xor tree over the 64 lanes, no barrier).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One wave per chunk of kChunk nodes: lane k takes nodes k, k + 64, k + 128, k + 192 of the
+// chunk in that order (every load stays coalesced), then the wave sums its lanes.
+constexpr int kLaneNodes = kChunk / 64;
+static_assert(kChunk % 64 == 0, "a chunk is whole waves of nodes");
+
+__global__ __launch_bounds__(64) void reduce_chunk_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
     int64_t N, const float* __restrict__ s, const float* __restrict__ s_ref, MsParamsDev P,
     double* __restrict__ partial) {
-  __shared__ double sh[256];
   const int t = blockIdx.x;
   const int b = chunk_inst[t];
   const InstDev I = inst[b];
-  const int local = (t - prefix[b]) * kChunk + (int)threadIdx.x;  // 32-bit: within one instance
+  const int N32 = (int)N;  // validated: 24 N < 2^32, so every element index below fits 31 bits
+  const int n_nodes = I.H * I.W;
+  const int first = (t - prefix[b]) * kChunk + (int)threadIdx.x;
+  // row and column of the lane's first node; each further node is 64 along the row-major order
+  int i = first / I.W, j = first - (first / I.W) * I.W;
+  const int di = 64 / I.W, dj = 64 - (64 / I.W) * I.W;
+  const double m = I.mass;
+  const double ge[3] = {(double)P.g[0] + I.ax, (double)P.g[1] + I.ay, (double)P.g[2] + I.az};
+  const double h = I.h;
+  const double L[3] = {h, 1.4142135623730951 * h, 2.0 * h};
+  const double ih = 1.0 / h;  // one division per lane; the stretch ratios multiply
+  const double iL[3] = {ih, 0.70710678118654752 * ih, 0.5 * ih};
   double e2 = 0.0, en = 0.0, st_s = 0.0, st_a = 0.0;
-  if (local < I.H * I.W) {
-    const int i = local / I.W, j = local - (local / I.W) * I.W;
-    const int64_t p = I.off + local;
-    const double m = I.mass;
-    const double ge[3] = {(double)P.g[0] + I.ax, (double)P.g[1] + I.ay, (double)P.g[2] + I.az};
+  for (int q = 0; q < kLaneNodes; ++q) {
+    const int local = first + 64 * q;
+    if (local >= n_nodes) break;
+    const int p = (int)I.off + local;
     double x[3];
     for (int a = 0; a < 3; ++a) {
-      x[a] = s[a * N + p];
-      const double v = s[(3 + a) * N + p];
+      x[a] = gld(s, (unsigned)(a * N32 + p));
+      const double v = gld(s, (unsigned)((3 + a) * N32 + p));
       en += 0.5 * m * v * v - m * ge[a] * x[a];
       if (s_ref) {
-        const double d = x[a] - (double)s_ref[a * N + p];
+        const double d = x[a] - (double)gld(s_ref, (unsigned)(a * N32 + p));
         e2 += d * d;
       }
     }
-    const double h = I.h;
-    const double L[3] = {h, 1.4142135623730951 * h, 2.0 * h};
-    const double ih = 1.0 / h;  // one division per node; the stretch ratios multiply
-    const double iL[3] = {ih, 0.70710678118654752 * ih, 0.5 * ih};
-    for (int q = 0; q < 6; ++q) {
-      const int ii = i + kHalf[q].dy, jj = j + kHalf[q].dx;
+    for (int k = 0; k < 6; ++k) {
+      const int ii = i + kHalf[k].dy, jj = j + kHalf[k].dx;
       // structural springs pointing backwards are visited by the other end; stretch needs all
       if (ii < 0 || ii >= I.H || jj < 0 || jj >= I.W) continue;
-      const int64_t pj = I.off + (int64_t)ii * I.W + jj;
+      const int pj = p + kHalf[k].dy * I.W + kHalf[k].dx;
       double d2 = 0.0;
       for (int a = 0; a < 3; ++a) {
-        const double d = x[a] - (double)s[a * N + pj];
+        const double d = x[a] - (double)gld(s, (unsigned)(a * N32 + pj));
         d2 += d * d;
       }
       const double r = sqrt(d2);
-      const int f = kHalf[q].fam;
+      const int f = kHalf[k].fam;
       const double dr = r - L[f];
       en += 0.5 * (double)P.k[f] * dr * dr;
       const double ratio = r * iL[f];
       if (f == 0) st_s = fmax(st_s, ratio);
       st_a = fmax(st_a, ratio);
     }
+    i += di;
+    j += dj;
+    if (j >= I.W) {
+      j -= I.W;
+      ++i;
+    }
   }
-  e2 = block_sum(e2, sh);
-  en = block_sum(en, sh);
-  st_s = block_max(st_s, sh);
-  st_a = block_max(st_a, sh);
+  e2 = wave_sum(e2);
+  en = wave_sum(en);
+  st_s = wave_max(st_s);
+  st_a = wave_max(st_a);
   if (threadIdx.x == 0) {
     partial[4 * t + 0] = e2;
     partial[4 * t + 1] = en;
@@ -127,7 +153,7 @@ int reduce_launch(const pecnn_plan* plan, const MsParamsDev& P, const float* s, 
                   void* ws, hipStream_t st) {
   const int nt = plan->n_tiles[kCfgChunk];
   double* partial = (double*)ws;
-  hipLaunchKernelGGL(reduce_chunk_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk],
+  hipLaunchKernelGGL(reduce_chunk_kernel, dim3(nt), dim3(64), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk],
                      plan->d_chunk_inst, plan->total, s, s_ref, P, partial);
   PECNN_LAUNCH_CHECK("reduce_chunk_kernel");
   hipLaunchKernelGGL(reduce_final_kernel, dim3(plan->n), dim3(256), 0, st, plan->d_prefix[kCfgChunk],

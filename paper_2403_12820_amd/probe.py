@@ -2,6 +2,7 @@
 
   python -m paper_2403_12820_amd.probe cnn   # bf16 CNN frame, 128 cloths of 256 x 256, Ch = 32
   python -m paper_2403_12820_amd.probe ms    # FP32 mass-spring step on the same batch
+  python -m paper_2403_12820_amd.probe reduce  # FP64 diagnostics (the rollout guard's check)
   python -m paper_2403_12820_amd.probe copy  # plain device copy of 1 GiB (counter calibration)
 """
 import sys
@@ -35,6 +36,11 @@ def main(kind: str, reps: int = 5, instances: int = 128, size: int = 256):
         sim = L.ms_params(mat)
         for i in range(reps):
             L.cloth_ms_step(plan, sim, bufs[i % 2], bufs[(i + 1) % 2], 1)
+    elif kind == "reduce":
+        sim = L.ms_params(mat)
+        out = torch.empty(4 * batch.n, dtype=torch.float64, device=dev)
+        for i in range(reps):
+            L.cloth_reduce_fp64(plan, sim, bufs[0], bufs[1], out)
     else:
         raise SystemExit("unknown probe " + kind)
     torch.cuda.synchronize()
