@@ -55,8 +55,14 @@ def measured_traffic(nodes):
     return float(tr["bytes_per_launch"])
 
 
-def load_theta(ch, cell="conv"):
+def load_theta(ch, cell="conv", path=None):
     from paper_2403_12820_amd import inputs as I
+    if path is not None:  # weights named on the command line: used as they are, or refused
+        th = np.load(path, allow_pickle=False).astype(np.float32)
+        need = I.PAIR_THETA_SIZE if cell == "pair" else I.theta_size(ch)
+        if th.size != need:
+            raise SystemExit("%s holds %d parameters, the %s cell needs %d" % (path, th.size, cell, need))
+        return th, "trained (%s)" % os.path.basename(path)
     if cell == "pair":
         if os.path.exists(PAIR_WEIGHTS):
             th = np.load(PAIR_WEIGHTS, allow_pickle=False).astype(np.float32)
@@ -132,6 +138,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cores", type=int, default=1, help="worker processes for the oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--weights", default=None, help="a .npy of the cell's parameters (default: the committed ones)")
     ap.add_argument("--cell", choices=("conv", "pair"), default="conv",
                     help="conv: the bf16 convolution cell (default); pair: the paper's own cell, FP32")
     args = ap.parse_args()
@@ -142,7 +149,7 @@ def main():
 
     pair = args.cell == "pair"
     ch = 12 if pair else args.ch
-    theta_np, theta_kind = load_theta(ch, args.cell)
+    theta_np, theta_kind = load_theta(ch, args.cell, args.weights)
     # the CPU baseline first, before anything touches the GPU
     cpu = None if args.no_cpu else cpu_baseline(ch, theta_np, args.cpu_seconds, args.cell, args.cpu_cores)
 

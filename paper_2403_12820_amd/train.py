@@ -246,69 +246,95 @@ def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0,
     return rms, b
 
 
+class SizeClass:
+    """Trajectories of one grid size with their loss scales, training and held-out windows."""
+
+    def __init__(self, size, n_scenes, n_val, seed, mat, n_frames, stride, n_win, n_unroll, device):
+        self.size = size
+        scenes = I.random_scenes([(size, size)] * n_scenes, seed=seed)
+        self.traj = Trajectories(scenes, mat, n_frames, stride, device)
+        self.sx, self.sv = self.traj.increment_scales()
+        self.train_ids = list(range(n_scenes - n_val))
+        self.val_ids = list(range(n_scenes - n_val, n_scenes))
+        self.wb = WindowBatch(self.traj, self.train_ids, n_win, n_unroll, device)
+        # fixed held-out windows for a deterministic validation loss
+        self.wv = WindowBatch(self.traj, self.val_ids, n_win, n_unroll, device)
+        self.val_plan, self.val_free = self.wv.sample(np.random.default_rng(seed + 1))
+
+
 def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=32, lr=1e-3, seed=4,
           n_frames=201, stride=10, log_every=500, eval_frames=100, device="cuda", verbose=True, lr_final=None,
-          alpha=0.0, cell="conv"):
+          alpha=0.0, cell="conv", sizes=None):
     """Adam at lr, annealed along a cosine to lr_final over the run when lr_final is given (the
-    post-process cosine schedule of Table 1); alpha weighs the physics term of eq. (8)."""
+    post-process cosine schedule of Table 1); alpha weighs the physics term of eq. (8).
+    sizes: grid sides trained together, n_scenes each (the first with `seed`, the others with
+    their own seeds); iterations take their minibatches from the sizes in turn, each size with
+    its own increment scales, and the kept theta has the lowest mean held-out error over them."""
     import torch
     mat = I.Material()
     t0 = time.time()
-    scenes = I.random_scenes([(size, size)] * n_scenes, seed=seed)
-    traj = Trajectories(scenes, mat, n_frames, stride, device)
-    sx, sv = traj.increment_scales()
+    sizes = [size] if not sizes else list(sizes)
+    classes = [SizeClass(sz, n_scenes, n_val, seed + 1000 * k, mat, n_frames, stride, n_win, n_unroll, device)
+               for k, sz in enumerate(sizes)]
     t_gen = time.time() - t0
-    train_ids = list(range(n_scenes - n_val))
-    val_ids = list(range(n_scenes - n_val, n_scenes))
-    wb = WindowBatch(traj, train_ids, n_win, n_unroll, device)
     tr = Trainer(ch=ch, dt_nn=stride * mat.dt, lr=lr, device=device, cell=cell)
     ch = tr.ch
     theta0 = tr.theta.cpu().numpy().copy()
     rng = np.random.default_rng(seed)
-    # fixed held-out windows for a deterministic validation loss
-    wv = WindowBatch(traj, val_ids, n_win, n_unroll, device)
-    val_plan, val_free = wv.sample(np.random.default_rng(seed + 1))
+
+    def val_rms(theta):
+        return [rollout_rms(c.traj, c.val_ids, theta, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
+                            cell=cell)[0] for c in classes]
+
+    def val_loss():
+        return float(np.mean([eval_loss(tr, c.wv, c.val_plan, c.val_free, c.sx, c.sv, alpha=alpha, sim=c.traj.sim,
+                                        stride=stride) for c in classes]))
+
     curve = []
     t1 = time.time()
     best = (math.inf, theta0)
     for it in range(1, iters + 1):
-        plan, n_free = wb.sample(rng)
+        c = classes[(it - 1) % len(classes)]
+        plan, n_free = c.wb.sample(rng)
         lr_t = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (it - 1) / iters))
-        loss = tr.step(wb, plan, n_free, sx, sv, lr=lr_t, alpha=alpha, sim=traj.sim, stride=stride)
+        loss = tr.step(c.wb, plan, n_free, c.sx, c.sv, lr=lr_t, alpha=alpha, sim=c.traj.sim, stride=stride)
         if it % log_every == 0 or it == 1 or it == iters:
             lv = float(loss.item())
-            vl = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
+            vl = val_loss()
             curve.append((it, lv, vl))
             if not np.isfinite(lv):
                 raise FloatingPointError("training diverged at iteration %d" % it)
-            rms_v, _ = rollout_rms(traj, val_ids, tr.theta.cpu().numpy(), ch, eval_frames, dt_nn=stride * mat.dt,
-                                   device=device, cell=cell)
-            if rms_v.mean() < best[0]:
-                best = (float(rms_v.mean()), tr.theta.cpu().numpy().copy())
+            rms_v = float(np.mean([r.mean() for r in val_rms(tr.theta.cpu().numpy())]))
+            if rms_v < best[0]:
+                best = (rms_v, tr.theta.cpu().numpy().copy())
             if verbose:
                 print("iter %6d loss %.5g  val loss %.5g  val rms@%d %.4g  (%.1f s)" % (
-                    it, lv, vl, eval_frames, rms_v.mean(), time.time() - t1), flush=True)
+                    it, lv, vl, eval_frames, rms_v, time.time() - t1), flush=True)
         plan.close()
     torch.cuda.synchronize()
     t_train = time.time() - t1
     theta_best = best[1]
-    rms_trained, _ = rollout_rms(traj, val_ids, theta_best, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
-                                 cell=cell)
-    rms_untrained, _ = rollout_rms(traj, val_ids, theta0, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
-                                   cell=cell)
-    val_loss_final = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
+    rms_trained = val_rms(theta_best)
+    rms_untrained = val_rms(theta0)
+    val_loss_final = val_loss()
     tr.theta.copy_(torch.tensor(theta_best, device=device))
-    val_loss_best = eval_loss(tr, wv, val_plan, val_free, sx, sv, alpha=alpha, sim=traj.sim, stride=stride)
+    val_loss_best = val_loss()
     report = {
-        "scenes": n_scenes, "grid": size, "val_scenes": n_val, "iters": iters, "minibatch": n_win,
-        "unroll": n_unroll, "cell": cell, "channels": ch, "lr": lr, "lr_final": lr_final, "alpha": alpha, "stride": stride,
-        "frames": n_frames,
-        "increment_scales": [sx, sv], "loss_curve": curve, "generation_s": t_gen, "train_s": t_train,
-        "val_rms_trained": rms_trained.tolist(), "val_rms_untrained": rms_untrained.tolist(),
-        "val_rms_trained_mean": float(rms_trained.mean()), "val_rms_untrained_mean": float(rms_untrained.mean()),
+        "scenes": n_scenes, "grid": sizes[0] if len(sizes) == 1 else sizes, "val_scenes": n_val, "iters": iters,
+        "minibatch": n_win, "unroll": n_unroll, "cell": cell, "channels": ch, "lr": lr, "lr_final": lr_final,
+        "alpha": alpha, "stride": stride, "frames": n_frames,
+        "increment_scales": [c.sx, c.sv] if len(classes) == 1 else [[c.sx, c.sv] for c in classes],
+        "loss_curve": curve, "generation_s": t_gen, "train_s": t_train,
+        "val_rms_trained": np.concatenate(rms_trained).tolist(),
+        "val_rms_untrained": np.concatenate(rms_untrained).tolist(),
+        "val_rms_trained_mean": float(np.mean([r.mean() for r in rms_trained])),
+        "val_rms_untrained_mean": float(np.mean([r.mean() for r in rms_untrained])),
         "eval_frames": eval_frames, "val_loss_first": curve[0][2], "val_loss_best_theta": val_loss_best,
         "val_loss_final_theta": val_loss_final,
     }
+    if len(classes) > 1:
+        report["val_rms_trained_by_size"] = {str(c.size): float(r.mean()) for c, r in zip(classes, rms_trained)}
+        report["val_rms_untrained_by_size"] = {str(c.size): float(r.mean()) for c, r in zip(classes, rms_untrained)}
     return theta_best, report
 
 
@@ -316,6 +342,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--scenes", type=int, default=64)
     ap.add_argument("--size", type=int, default=64)
+    ap.add_argument("--sizes", default=None, help="comma-separated grid sides trained together (overrides --size)")
     ap.add_argument("--val", type=int, default=8)
     ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--minibatch", type=int, default=32)
@@ -332,7 +359,7 @@ def main():
     args = ap.parse_args()
     theta, report = train(args.scenes, args.size, args.val, args.iters, args.minibatch, args.unroll, args.ch,
                           args.lr, args.seed, log_every=args.log_every, lr_final=args.lr_final, alpha=args.alpha,
-                          cell=args.cell)
+                          cell=args.cell, sizes=[int(x) for x in args.sizes.split(",")] if args.sizes else None)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, theta.astype(np.float32), allow_pickle=False)
     rep = args.report or os.path.splitext(args.out)[0] + "_report.json"
