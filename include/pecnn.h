@@ -17,6 +17,11 @@
  * allocated only for plan handles (pecnn_plan_create / pecnn_plan_destroy) and the
  * rollout's graph cache inside a plan (its graphs, a capture stream and one pinned int).
  *
+ * Threads: entry points that take a const plan may run concurrently from several host threads
+ * (with distinct outputs and workspaces). pecnn_rollout, pecnn_autotune, pecnn_plan_set_* and
+ * pecnn_plan_destroy change the plan (its tile choice, records or graph cache): the caller
+ * serialises them against every other call on the same plan.
+ *
  * Errors: every entry point validates its arguments before any launch and returns a
  * negative pecnn_status with no side effect on invalid input. A failed HIP call returns
  * PECNN_E_HIP; pecnn_last_error() gives a message (thread-local). Kernel faults surface at
