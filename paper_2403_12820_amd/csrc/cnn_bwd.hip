@@ -358,9 +358,8 @@ __global__ __launch_bounds__(256) void bwd_wgrad_kernel(const float* __restrict_
   constexpr int TPW = (NT + 3) / 4;                      // tiles per wave
   constexpr BwdLayout L = bwd_layout(CH);
   constexpr int ROWS = L.rows;
-  constexpr int R = ROWS + 16;        // pad block: a ones row, then zeros
   constexpr int LS = kWgSub + 4;      // LDS row stride (bank spread)
-  extern __shared__ float lds[];      // [R][LS]
+  extern __shared__ float lds[];      // [ROWS + 16][LS]: the rows, then a pad block (a ones row, then zeros)
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
