@@ -119,6 +119,55 @@ def cpu_baseline(ch, theta, budget_s=10.0, cell="conv", cores=1, stride=10):
                           frames, what, cores, "" if cores == 1 else "es", max(t for _, t in res), stride)}
 
 
+def _oracle_suite_worker(args):
+    """One worker: repeated oracle calls of one workload for budget_s; returns (node-steps, seconds)."""
+    kind, size, budget_s, seed = args
+    import oracle
+    from paper_2403_12820_amd import inputs as I
+    mat = I.Material()
+    sc = I.random_scenes([(size, size)], seed=seed)[0]
+    s = sc.state.astype(np.float64)
+    s[3:] = I.random_array((3, size * size), seed=seed + 1, scale=0.05)
+    th = I.init_theta(32, seed=1).astype(np.float64)
+    g = I.random_array((6, size * size), seed=seed + 2)
+    steps = max(1, 4096 * 200 // (size * size)) if kind == "ms" else 1
+    done, t0 = 0, time.perf_counter()
+    while True:
+        if kind == "ms":
+            oracle.ms_run(size, size, sc.h, sc.mass, sc.a_ext, sc.pin, s, mat, steps)
+        elif kind == "cnn":
+            oracle.cnn_forward(size, size, 32, 1.0, 5e-3, sc.a_ext, sc.pin, th, s, s)
+        else:
+            oracle.cnn_backward(size, size, 32, 1.0, 5e-3, sc.pin, th, s, s, g)
+        done += steps * size * size
+        if time.perf_counter() - t0 >= budget_s:
+            return done, time.perf_counter() - t0
+
+
+def cpu_suite(cores, budget_s=4.0):
+    """The oracle's own speed on the host: the mass-spring step at three sizes, the CNN frame and
+    its backward pass (Ch = 32), each on one worker and on `cores` workers (independent cloths),
+    in nodes x steps (frames for the CNN) per second. Touches no GPU."""
+    import multiprocessing as mp
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
+    rows = []
+    for kind, size, unit in (("ms", 32, "node-steps/s"), ("ms", 128, "node-steps/s"), ("ms", 256, "node-steps/s"),
+                             ("cnn", 256, "node-frames/s"), ("bwd", 64, "node-frames/s (backward)")):
+        one = _oracle_suite_worker((kind, size, budget_s, 11))
+        with mp.get_context("fork").Pool(cores) as pool:
+            many = pool.map(_oracle_suite_worker, [(kind, size, budget_s, 11 + k) for k in range(cores)])
+        rows.append({"workload": "%s %dx%d" % ({"ms": "FP64 mass-spring step", "cnn": "FP64 CNN frame, Ch=32",
+                                                  "bwd": "FP64 CNN backward, Ch=32"}[kind], size, size),
+                     "unit": unit, "one_core": one[0] / one[1], "all_cores": sum(n / t for n, t in many),
+                     "cores": cores})
+    return {"cpu_suite": rows, "host_cpu": cpu, "nproc": os.cpu_count(), "kind": "oracle"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,14 +187,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cores", type=int, default=1, help="worker processes for the oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-suite", action="store_true",
+                    help="time the oracle on the host (mass-spring, CNN frame, backward; one and --cpu-cores workers) and exit")
     ap.add_argument("--weights", default=None, help="a .npy of the cell's parameters (default: the committed ones)")
     ap.add_argument("--cell", choices=("conv", "pair"), default="conv",
                     help="conv: the bf16 convolution cell (default); pair: the paper's own cell, FP32")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (instances would shard "
-              "across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (cloths would shard "
+              "across GPUs by node count, with no exchange during the rollout)", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_suite:
+        print(json.dumps(cpu_suite(max(1, args.cpu_cores))))
+        return
 
     pair = args.cell == "pair"
     ch = 12 if pair else args.ch
