@@ -317,9 +317,21 @@ struct WgTile {
   int xb, yb;    // block indices inside the parameter
 };
 
+// The weight sums never read the adjoints of the im2col entries (rows gus and gud, for the input
+// gradients): the kernel stages the other rows only, and table row r >= L.phi sits at LDS row
+// r - kWgSkip. wg_tile gives rows in that LDS numbering.
+constexpr int kWgSkip = 108;  // rows gus and gud
+template <int CH>
+__host__ __device__ constexpr int wg_rows() { return bwd_layout(CH).rows - kWgSkip; }
+
 template <int CH>
 __device__ __forceinline__ WgTile wg_tile(int t) {
-  constexpr BwdLayout L = bwd_layout(CH);
+  constexpr BwdLayout L0 = bwd_layout(CH);
+  static_assert(L0.gus == L0.ud + 54 && L0.phi == L0.gus + kWgSkip, "gus and gud lie between ud and phi");
+  // the layout with the skipped rows taken out
+  constexpr BwdLayout L = {L0.uk, L0.ud, -1, -1, L0.phi - kWgSkip, L0.nn - kWgSkip, L0.dd - kWgSkip,
+                           L0.ga - kWgSkip, L0.gb - kWgSkip, L0.gphi - kWgSkip, L0.gxi - kWgSkip,
+                           L0.gdv - kWgSkip, L0.rows - kWgSkip};
   constexpr int MB = CH / 16;
   WgTile T;
   T.x1 = T.y1 = -1;
@@ -357,9 +369,10 @@ __global__ __launch_bounds__(256) void bwd_wgrad_kernel(const float* __restrict_
   constexpr int NT = MB * 4 + 2 * MB * MB + 3 * MB + 1;  // output tiles
   constexpr int TPW = (NT + 3) / 4;                      // tiles per wave
   constexpr BwdLayout L = bwd_layout(CH);
-  constexpr int ROWS = L.rows;
+  constexpr int ROWS = L.rows;        // rows of a table block
+  constexpr int WROWS = wg_rows<CH>(); // rows staged: all but gus and gud
   constexpr int LS = kWgSub + 4;      // LDS row stride (bank spread)
-  extern __shared__ float lds[];      // [ROWS + 16][LS]: the rows, then a pad block (a ones row, then zeros)
+  extern __shared__ float lds[];      // [WROWS + 16][LS]: the rows, then a pad block (a ones row, then zeros)
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -367,23 +380,25 @@ __global__ __launch_bounds__(256) void bwd_wgrad_kernel(const float* __restrict_
   const int64_t n0 = (int64_t)blockIdx.x * NB;
   const int64_t n1 = min(N, n0 + NB);
 
-  for (int e = threadIdx.x; e < 16 * LS; e += 256) lds[ROWS * LS + e] = (e < kWgSub) ? 1.f : 0.f;
+  for (int e = threadIdx.x; e < 16 * LS; e += 256) lds[WROWS * LS + e] = (e < kWgSub) ? 1.f : 0.f;
 
   // a round is one node block of the table: ROWS x 32 contiguous floats; this thread stages the
-  // float4 number tid + 256 i of it (row e4 / 8, nodes 4 (e4 % 8) .. +3)
+  // float4 number tid + 256 i of its staged rows (LDS row e4 / 8, nodes 4 (e4 % 8) .. +3), which
+  // is float4 e4 of the block before row gus and e4 + 8 kWgSkip after it
   typedef float f32x4 __attribute__((ext_vector_type(4)));
-  constexpr int Q = ROWS * (kWgSub / 4);  // float4s per round
+  constexpr int Q = WROWS * (kWgSub / 4);  // float4s per round
   constexpr int PF = (Q + 255) / 256;
   f32x4 pf[PF];
   const int c4 = (threadIdx.x & 7) * 4;
   auto fetch = [&](int64_t s) {
-    const f32x4* src = reinterpret_cast<const f32x4*>(fac + (s >> 5) * (int64_t)(ROWS * 32)) + threadIdx.x;
+    const f32x4* src = reinterpret_cast<const f32x4*>(fac + (s >> 5) * (int64_t)(ROWS * 32));
     const int64_t left = n1 - s - c4;  // valid nodes from this thread's first column
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (threadIdx.x + 256 * i < Q && left > 0) {
-        v = src[256 * i];
+      const int e4 = (int)threadIdx.x + 256 * i;
+      if (e4 < Q && left > 0) {
+        v = src[e4 < L.gus * 8 ? e4 : e4 + 8 * kWgSkip];
         if (left < 4) {  // block tail: table padding beyond the last node is not initialised
           v[3] = 0.f;
           if (left < 3) v[2] = 0.f;
@@ -660,7 +675,7 @@ int backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* s
                        gn, plan->total, m->dt, m->ch, fac, gc, gp);
     PECNN_LAUNCH_CHECK("bwd_gather_kernel");
   }
-  const size_t lds = (size_t)(L.rows + 16) * (kWgSub + 4) * sizeof(float);
+  const size_t lds = (size_t)(L.rows - kWgSkip + 16) * (kWgSub + 4) * sizeof(float);
   const int64_t nb = wgrad_nodes_per_block(plan->total);
   const int nrows = (int)wgrad_blocks(plan->total);
   if (m->ch == 16)
