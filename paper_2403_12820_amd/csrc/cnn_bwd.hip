@@ -465,21 +465,24 @@ __global__ __launch_bounds__(256) void bwd_wgrad_kernel(const float* __restrict_
   }
 }
 
-// g_theta[e] += sum over the partial rows in index order: 16 lanes per parameter each sum a fixed
-// stride of rows, then a fixed-order combine in LDS (deterministic).
-__global__ __launch_bounds__(1024) void wgrad_final_kernel(const float* __restrict__ partial, int n_rows, int P,
-                                                           float* __restrict__ g_theta) {
-  __shared__ double sh[16][64];
-  const int pl = threadIdx.x & 63, r0 = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + pl;
+// g_theta[e] += sum over the partial rows: 32 threads per parameter each sum a fixed stride of
+// rows, then a fixed-order combine in LDS (deterministic). 32 parameters per workgroup, so that a
+// batch of 4,067 parameters spreads over 128 workgroups.
+constexpr int kWfParams = 32, kWfGroups = 32;
+__global__ __launch_bounds__(kWfParams * kWfGroups) void wgrad_final_kernel(const float* __restrict__ partial,
+                                                                            int n_rows, int P,
+                                                                            float* __restrict__ g_theta) {
+  __shared__ double sh[kWfGroups][kWfParams + 1];
+  const int pl = threadIdx.x % kWfParams, r0 = threadIdx.x / kWfParams;
+  const int e = blockIdx.x * kWfParams + pl;
   double s = 0.0;
   if (e < P)
-    for (int r = r0; r < n_rows; r += 16) s += (double)partial[(int64_t)r * P + e];
+    for (int r = r0; r < n_rows; r += kWfGroups) s += (double)partial[(int64_t)r * P + e];
   sh[r0][pl] = s;
   __syncthreads();
   if (r0 == 0 && e < P) {
     double t = 0.0;
-    for (int k = 0; k < 16; ++k) t += sh[k][pl];
+    for (int k = 0; k < kWfGroups; ++k) t += sh[k][pl];
     g_theta[e] += (float)t;
   }
 }
@@ -640,7 +643,8 @@ int pair_backward_launch(const pecnn_plan* plan, const pecnn_model* m, const flo
   hipLaunchKernelGGL(pair_wgrad_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, sc,
                      gn, plan->total, m->theta, m->isru_alpha, m->dt, partial);
   PECNN_LAUNCH_CHECK("pair_wgrad_kernel");
-  hipLaunchKernelGGL(wgrad_final_kernel, dim3(1), dim3(1024), 0, st, partial, nt, kPairP, gth);
+  hipLaunchKernelGGL(wgrad_final_kernel, dim3((kPairP + kWfParams - 1) / kWfParams), dim3(kWfParams * kWfGroups), 0,
+                     st, partial, nt, kPairP, gth);
   PECNN_LAUNCH_CHECK("wgrad_final_kernel");
   return PECNN_OK;
 }
@@ -683,7 +687,8 @@ int backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* s
   else
     hipLaunchKernelGGL(bwd_wgrad_kernel<32>, dim3(nrows), dim3(256), lds, st, fac, plan->total, nb, partial);
   PECNN_LAUNCH_CHECK("bwd_wgrad_kernel");
-  hipLaunchKernelGGL(wgrad_final_kernel, dim3((P + 63) / 64), dim3(1024), 0, st, partial, nrows, P, gth);
+  hipLaunchKernelGGL(wgrad_final_kernel, dim3((P + kWfParams - 1) / kWfParams), dim3(kWfParams * kWfGroups), 0, st,
+                     partial, nrows, P, gth);
   PECNN_LAUNCH_CHECK("wgrad_final_kernel");
   return PECNN_OK;
 }
