@@ -245,33 +245,48 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
             float f0 = __builtin_fmaf(-P.drag, v0, g0);
             float f1 = __builtin_fmaf(-P.drag, v1, g1);
             float f2 = __builtin_fmaf(-P.drag, v2, g2);
-            // One spring loop, two instances: tiles whose springs all have both ends on the grid
-            // skip the per-spring end checks (about 30% fewer VALU instructions per node). A
-            // degenerate spring (r ~ 0) contributes nothing in both: with ir = 0 both
-            // coefficients vanish.
-            auto springs = [&](auto checked) {
+            // One spring loop, two instances. Tiles whose springs all have both ends on the grid take
+            // every spring as it is. Edge tiles take the same loop and zero the coefficient of a
+            // spring whose far end is off the grid: that end reads a clamped copy in the halo, so
+            // every value stays finite, and a zero coefficient adds nothing to the force. Eight
+            // comparisons per node and one select per spring replace a branch per spring. A
+            // degenerate spring (r ~ 0) contributes nothing either: with ir = 0 both coefficients
+            // vanish.
+            auto springs = [&](auto masked) {
+              bool u1 = true, u2 = true, d1 = true, d2 = true, l1 = true, l2 = true, r1 = true, r2 = true;
+              if constexpr (decltype(masked)::value) {
+                u1 = i >= 1;
+                u2 = i >= 2;
+                d1 = i + 1 < Ic.H;
+                d2 = i + 2 < Ic.H;
+                l1 = j >= 1;
+                l2 = j >= 2;
+                r1 = j + 1 < Ic.W;
+                r2 = j + 2 < Ic.W;
+              }
 #pragma unroll
               for (int q = 0; q < 12; ++q) {
                 const Spring S = kSprings[q];
-                if constexpr (decltype(checked)::value) {
-                  const int ii = i + S.dy, jj = j + S.dx;
-                  if (ii < 0 || ii >= Ic.H || jj < 0 || jj >= Ic.W) continue;  // spring needs both ends
-                }
                 const int en = e + S.dy * RS + S.dx;
-                const float d0 = x0 - lds[en], d1 = x1 - lds[PLN + en], d2 = x2 - lds[2 * PLN + en];
+                const float d0 = x0 - lds[en], d1_ = x1 - lds[PLN + en], d2_ = x2 - lds[2 * PLN + en];
                 const float w0 = v0 - lds[3 * PLN + en], w1 = v1 - lds[4 * PLN + en], w2 = v2 - lds[5 * PLN + en];
-                const float r2 = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
-                const float ir = r2 > tiny ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                const float r = r2 * ir;
-                const float ce = (P.k[S.fam] * (L[S.fam] - r)) * ir;       // eq. (1): -k (r - L) / r
-                const float vx = __builtin_fmaf(w2, d2, __builtin_fmaf(w1, d1, w0 * d0));
-                const float cf = __builtin_fmaf((nmu * ir) * ir, vx, ce);  // eq. (2): -mu (v.x) / r^2
+                const float rr = __builtin_fmaf(d2_, d2_, __builtin_fmaf(d1_, d1_, d0 * d0));
+                const float ir = rr > tiny ? __builtin_amdgcn_rsqf(rr) : 0.f;
+                const float r = rr * ir;
+                const float ce = (P.k[S.fam] * (L[S.fam] - r)) * ir;  // eq. (1): -k (r - L) / r
+                const float vx = __builtin_fmaf(w2, d2_, __builtin_fmaf(w1, d1_, w0 * d0));
+                float cf = __builtin_fmaf((nmu * ir) * ir, vx, ce);   // eq. (2): -mu (v.x) / r^2
+                if constexpr (decltype(masked)::value) {
+                  const bool rok = S.dy == 0 ? true : S.dy == 1 ? d1 : S.dy == 2 ? d2 : S.dy == -1 ? u1 : u2;
+                  const bool cok = S.dx == 0 ? true : S.dx == 1 ? r1 : S.dx == 2 ? r2 : S.dx == -1 ? l1 : l2;
+                  cf = (rok && cok) ? cf : 0.f;
+                }
                 f0 = __builtin_fmaf(cf, d0, f0);
-                f1 = __builtin_fmaf(cf, d1, f1);
-                f2 = __builtin_fmaf(cf, d2, f2);
-                // compiler fence in the unchecked loop: each spring's LDS reads stay next to their
-                // use instead of all 72 being hoisted, which would cost occupancy
-                if constexpr (!decltype(checked)::value) asm volatile("" ::: "memory");
+                f1 = __builtin_fmaf(cf, d1_, f1);
+                f2 = __builtin_fmaf(cf, d2_, f2);
+                // compiler fence: each spring's LDS reads stay next to their use instead of all 72
+                // being hoisted, which would cost occupancy
+                asm volatile("" ::: "memory");
               }
             };
             // workgroup-uniform: every spring of every node of the tile has both ends on the grid
