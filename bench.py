@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--stretch-max", type=float, default=2.0)
     ap.add_argument("--energy-gain-max", type=float, default=0.2)
+    ap.add_argument("--frame-err-max", type=float, default=0.0,
+                    help="bound of the guard's frame-error test (RMS / width of one frame against the "
+                         "simulator); 0 = off")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -242,6 +245,7 @@ def main():
     guard = L.Guard()
     guard.stretch_max, guard.energy_gain_max = args.stretch_max, args.energy_gain_max
     guard.check_every, guard.substeps = args.check_every, stride
+    guard.frame_err_max = args.frame_err_max
     fb = torch.zeros(batch.n, dtype=torch.int32, device=dev)
     stats = torch.zeros(4 * batch.n, dtype=torch.float64, device=dev)
     ws = plan.workspace(L.WS_ROLLOUT)
@@ -329,7 +333,7 @@ def main():
             "rms_vs_fp32_ms_width_mean": float(rms.mean()), "rms_vs_fp32_ms_width_max": float(rms.max()),
             "rms_bound": 1e-2, "rms_within_bound": bool(rms.max() <= 1e-2),
             "guard": {"stretch_max": args.stretch_max, "energy_gain_max": args.energy_gain_max,
-                      "check_every": args.check_every},
+                      "check_every": args.check_every, "frame_err_max": args.frame_err_max},
             "fallback_instances": fell, "fallback_rate": fell / batch.n,
             "fallback_node_fraction": float(sum(int(batch.H[b]) * int(batch.W[b]) for b in np.nonzero(fb_host)[0])) / N,
             "ms_kernel_gbs": MS_BYTES_PER_NODE * N / t_ms_kernel / 1e9,

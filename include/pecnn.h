@@ -186,12 +186,21 @@ int pecnn_backward(const pecnn_plan* plan, const pecnn_model* model, const float
    gain (E_now - E_start)/E_ref exceeds energy_gain_max (E_ref = total mass |g| (W-1) h; no
    energy check for instances with a pressure, which does work on the cloth), the
    instance falls back for good to the mass-spring step with 'substeps' steps of sim->dt per
-   network step (substeps * sim->dt should equal model->dt). check_every <= 0 disables it. */
+   network step (substeps * sim->dt should equal model->dt). check_every <= 0 disables it.
+   frame_err_max > 0 adds a third test at every check, an online physics residual (eq. (8)
+   measures the network against the equations in its physics term; here positions are
+   compared): the last network step of the chunk is compared with 'substeps' mass-spring steps
+   from the same input state, and an instance whose position RMS over its nodes, divided by its
+   width (W-1) h, exceeds frame_err_max falls back. That costs
+   'substeps' mass-spring steps of the whole batch per check. The frame that tripped a test is
+   kept; the fall-back starts with the next one. frame_err_max <= 0 disables the test; NaN is
+   an error. */
 typedef struct {
   float stretch_max;
   float energy_gain_max;
   int32_t check_every;
   int32_t substeps;
+  float frame_err_max;
 } pecnn_guard;
 
 /* n_steps network frames of the whole batch. In/out: s_prev = S^{k-1}, s_cur = S^k; on return

@@ -41,7 +41,7 @@ class Model(C.Structure):
 
 class Guard(C.Structure):
     _fields_ = [("stretch_max", C.c_float), ("energy_gain_max", C.c_float), ("check_every", C.c_int32),
-                ("substeps", C.c_int32)]
+                ("substeps", C.c_int32), ("frame_err_max", C.c_float)]
 
 
 _lib = None

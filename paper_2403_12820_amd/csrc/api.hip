@@ -133,15 +133,20 @@ static void graph_cache_free(pecnn_plan* plan) {
 // ---------------------------------------------------------------- guard kernels
 // Every check: per instance, compare the largest structural stretch ratio and the energy gain
 // with the guard's bounds (no energy check where the energy scale is infinite: instances with a
-// pressure); a tripped instance falls back for good. Also counts fallen instances.
+// pressure) and, when the frame-error test is on, the squared position difference from the
+// simulator's frame times escale = 1 / (nodes width^2) with the squared bound; a tripped
+// instance falls back for good. Also counts fallen instances.
 // count[0] receives the number of fallen instances, count[1] keeps the index of the check.
 __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restrict__ now, double* __restrict__ e0,
-                                                    const double* __restrict__ eref, pecnn_guard G, int init,
+                                                    const double* __restrict__ eref,
+                                                    const double* __restrict__ escale, pecnn_guard G, int init,
                                                     int32_t* __restrict__ fallback, uint8_t* __restrict__ active_ms,
                                                     double* __restrict__ stats, int* __restrict__ count) {
   __shared__ int sh[256];
   const int chk = init ? 0 : count[1] + 1;
   const int step = chk * G.check_every;
+  const bool ferr = G.frame_err_max > 0.f;
+  const double ferr2 = (double)G.frame_err_max * (double)G.frame_err_max;
   int cnt = 0;
   for (int b = threadIdx.x; b < n; b += 256) {
     const double e = now[4 * b + 1], st = now[4 * b + 2];
@@ -152,7 +157,8 @@ __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restr
       stats[4 * b + 3] = fallback[b] ? 0.0 : -1.0;
     } else if (fallback[b] == 0 &&
                (!(st <= (double)G.stretch_max) ||
-                (isfinite(eref[b]) && !((e - e0[b]) / eref[b] <= (double)G.energy_gain_max)))) {
+                (isfinite(eref[b]) && !((e - e0[b]) / eref[b] <= (double)G.energy_gain_max)) ||
+                (ferr && !(now[4 * b] * escale[b] <= ferr2)))) {
       fallback[b] = 1;
       stats[4 * b + 3] = step;
     }
@@ -180,6 +186,7 @@ struct RolloutWs {
   double* now;     // [4n] diagnostics of the current check
   double* e0;      // [n] energy at the start
   double* eref;    // [n] energy scale
+  double* escale;  // [n] 1 / (nodes width^2) for the frame-error test
   double* stats;   // [4n] used when the caller passes NULL
   uint8_t* active; // [n]
   int* count;      // [1]
@@ -197,6 +204,7 @@ static RolloutWs rollout_layout(const pecnn_plan* plan, void* base) {
   w.now = (double*)(p + o); o += align256(4 * (size_t)plan->n * sizeof(double));
   w.e0 = (double*)(p + o); o += align256((size_t)plan->n * sizeof(double));
   w.eref = (double*)(p + o); o += align256((size_t)plan->n * sizeof(double));
+  w.escale = (double*)(p + o); o += align256((size_t)plan->n * sizeof(double));
   w.stats = (double*)(p + o); o += align256(4 * (size_t)plan->n * sizeof(double));
   w.active = (uint8_t*)(p + o); o += align256((size_t)plan->n);
   w.count = (int*)(p + o); o += 256;
@@ -584,7 +592,10 @@ int pecnn_gather_windows(const float* traj, int64_t traj_nodes, int32_t n_saved,
 }
 
 // ---------------------------------------------------------------- rollout
-// Record the network steps of one chunk (and the guard check that ends it) on 'st'.
+// Record the network steps of one chunk (and the guard check that ends it) on 'st'. With the
+// frame-error test on, the simulator's answer for the chunk's last frame is written into the
+// third buffer, which after the last rotation holds nothing the rollout still needs (the next
+// frame overwrites it).
 static int record_chunk(pecnn_plan* p, const pecnn_model* m, const MsParamsDev& sim, const pecnn_guard* g,
                         float* const buf[3], float* T, int len, bool with_ms, bool guard_on, int32_t* fallback,
                         double* stats, const RolloutWs& w, hipStream_t st) {
@@ -604,10 +615,15 @@ static int record_chunk(pecnn_plan* p, const pecnn_model* m, const MsParamsDev& 
     X = t;
   }
   if (guard_on) {
-    int rc = reduce_launch(p, sim, C, nullptr, w.now, w.part, st);
+    const bool ferr = g->frame_err_max > 0.f;
+    if (ferr) {
+      int rc = ms_step_run(p, p->ms_cfg, sim, P, X, T, g->substeps, nullptr, st);
+      if (rc) return rc;
+    }
+    int rc = reduce_launch(p, sim, C, ferr ? X : nullptr, w.now, w.part, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, *g, 0, fallback,
-                       w.active, stats, w.count);
+    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 0,
+                       fallback, w.active, stats, w.count);
     PECNN_LAUNCH_CHECK("guard_kernel");
   }
   return PECNN_OK;
@@ -623,7 +639,7 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
   if (!g || !s_prev || !s_cur || !fallback) { set_error("null guard, state or fallback flags"); return PECNN_E_INVALID; }
   if (n_steps < 0) { set_error("n_steps must be >= 0"); return PECNN_E_INVALID; }
   if (g->substeps < 1 || g->substeps > 1000) { set_error("guard substeps must be in [1, 1000]"); return PECNN_E_INVALID; }
-  if (g->check_every > 0 && (!(g->stretch_max > 0.f) || isnan(g->energy_gain_max))) {
+  if (g->check_every > 0 && (!(g->stretch_max > 0.f) || isnan(g->energy_gain_max) || isnan(g->frame_err_max))) {
     set_error("guard bounds must be > 0 / not NaN");
     return PECNN_E_INVALID;
   }
@@ -650,19 +666,22 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
 
   // prologue: energy scale, starting diagnostics, fall-back mask
   {
-    std::vector<double> eref(p->n);
+    std::vector<double> eref(p->n), escale(p->n);
     const double gn = sqrt((double)simp->g[0] * simp->g[0] + (double)simp->g[1] * simp->g[1] + (double)simp->g[2] * simp->g[2]);
     for (int b = 0; b < p->n; ++b) {
       double e = (double)p->H[b] * p->W[b] * p->mass[b] * (gn > 0 ? gn : 1.0) * (p->W[b] > 1 ? p->W[b] - 1 : 1) * p->h[b];
       eref[b] = e > 0 ? e : 1.0;
       // pressure does work on the cloth, so its energy may rise: the energy check is off there
       if (p->pres[b] != 0.f) eref[b] = INFINITY;
+      const double width = (double)(p->W[b] > 1 ? p->W[b] - 1 : 1) * p->h[b];
+      escale[b] = 1.0 / ((double)p->H[b] * p->W[b] * width * width);
     }
     PECNN_HIP(hipMemcpyAsync(w.eref, eref.data(), sizeof(double) * p->n, hipMemcpyHostToDevice, st));
+    PECNN_HIP(hipMemcpyAsync(w.escale, escale.data(), sizeof(double) * p->n, hipMemcpyHostToDevice, st));
     rc = reduce_launch(p, sim, s_cur, nullptr, w.now, w.part, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, *g, 1, fallback,
-                       w.active, stats_d, w.count);
+    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 1,
+                       fallback, w.active, stats_d, w.count);
     PECNN_LAUNCH_CHECK("guard_kernel");
     PECNN_HIP(hipMemcpyAsync(gc->host_count, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
     PECNN_HIP(hipStreamSynchronize(st));
