@@ -63,11 +63,11 @@ def _load():
         _lib.or_theta_size.argtypes = [i]
         _lib.or_theta_size.restype = l
         _lib.or_cnn_forward.argtypes = [i, i, i, d, d, p, d, p, p, p, p, p, i, p, p]
-        _lib.or_cnn_backward.argtypes = [i, i, i, d, d, d, p, p, p, p, p, p, p, p]
+        _lib.or_cnn_backward.argtypes = [i, i, i, d, d, p, d, p, p, p, p, p, p, p, p, p]
         _lib.or_pair_theta_size.argtypes = []
         _lib.or_pair_theta_size.restype = l
         _lib.or_pair_forward.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p]
-        _lib.or_pair_backward.argtypes = [i, i, d, d, d, p, p, p, p, p, p]
+        _lib.or_pair_backward.argtypes = [i, i, d, d, p, d, p, p, p, p, p, p, p]
         _lib.or_loss_mse.argtypes = [l, p, l, d, d, d, p, p, p]
         _lib.or_loss_mse.restype = d
         _lib.or_adam.argtypes = [l, d, d, d, d, i, p, p, p, p]
@@ -164,13 +164,16 @@ def cnn_forward(H, W, ch, alpha, dt, a_ext, pin, theta, s_prev, s_cur, emu=0, pm
     return out, dv
 
 
-def cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev, s_cur, g_next, pm=0.0):
-    """Returns (g_cur, g_prev, g_theta) for g_next = dLoss/dS^{k+1}."""
+def cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev, s_cur, g_next, pm=0.0, a_ext=(0.0, 0.0, 0.0),
+                 sphere=None):
+    """Returns (g_cur, g_prev, g_theta) for g_next = dLoss/dS^{k+1}. a_ext matters only with a
+    sphere (the constraint's adjoint needs the velocity before it)."""
     sp, sc, gn = (_f64(x).reshape(6, H * W) for x in (s_prev, s_cur, g_next))
-    th, pn = _f64(theta), _u8(pin)
+    th, pn, a = _f64(theta), _u8(pin), _f64(a_ext)
     gc, gp, gt = np.zeros((6, H * W)), np.zeros((6, H * W)), np.zeros(th.size)
-    _load().or_cnn_backward(H, W, ch, alpha, dt, float(pm), _ptr(pn), _ptr(th), _ptr(sp), _ptr(sc), _ptr(gn),
-                            _ptr(gc), _ptr(gp), _ptr(gt))
+    sph = _sphere(sphere)
+    _load().or_cnn_backward(H, W, ch, alpha, dt, _ptr(a), float(pm), _ptr(pn), _ptr(th), _ptr(sp), _ptr(sc),
+                            _ptr(gn), _ptr(gc), _ptr(gp), _ptr(gt), _ptr(sph) if sph is not None else None)
     return gc, gp, gt
 
 
@@ -190,12 +193,14 @@ def pair_forward(H, W, alpha, dt, a_ext, pin, theta, s_cur, pm=0.0, sphere=None)
     return out, dv
 
 
-def pair_backward(H, W, alpha, dt, pin, theta, s_cur, g_next, pm=0.0):
-    """Returns (g_cur, g_theta) for g_next = dLoss/dS^{k+1}."""
+def pair_backward(H, W, alpha, dt, pin, theta, s_cur, g_next, pm=0.0, a_ext=(0.0, 0.0, 0.0), sphere=None):
+    """Returns (g_cur, g_theta) for g_next = dLoss/dS^{k+1}. a_ext matters only with a sphere."""
     sc, gn = _f64(s_cur).reshape(6, H * W), _f64(g_next).reshape(6, H * W)
-    th, pn = _f64(theta), _u8(pin)
+    th, pn, a = _f64(theta), _u8(pin), _f64(a_ext)
     gc, gt = np.zeros((6, H * W)), np.zeros(th.size)
-    _load().or_pair_backward(H, W, alpha, dt, float(pm), _ptr(pn), _ptr(th), _ptr(sc), _ptr(gn), _ptr(gc), _ptr(gt))
+    sph = _sphere(sphere)
+    _load().or_pair_backward(H, W, alpha, dt, _ptr(a), float(pm), _ptr(pn), _ptr(th), _ptr(sc), _ptr(gn), _ptr(gc),
+                             _ptr(gt), _ptr(sph) if sph is not None else None)
     return gc, gt
 
 
@@ -263,7 +268,7 @@ def batch_cnn_backward(batch, ch, alpha, dt, theta, s_prev, s_cur, g_next):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
         c, p, t = cnn_backward(H, W, ch, alpha, dt, pin, theta, s_prev[:, sl], s_cur[:, sl], g_next[:, sl],
-                               _pressure(batch, b) / m)
+                               _pressure(batch, b) / m, a, _batch_sphere(batch, b))
         gc[:, sl] += c
         gp[:, sl] += p
         gt += t
@@ -288,7 +293,8 @@ def batch_pair_backward(batch, alpha, dt, theta, s_cur, g_next):
     for b in range(batch.n):
         H, W, h, m, a, pin = _inst(batch, b)
         sl = batch.instance(b)
-        c, t = pair_backward(H, W, alpha, dt, pin, theta, s_cur[:, sl], g_next[:, sl], _pressure(batch, b) / m)
+        c, t = pair_backward(H, W, alpha, dt, pin, theta, s_cur[:, sl], g_next[:, sl], _pressure(batch, b) / m,
+                             a, _batch_sphere(batch, b))
         gc[:, sl] += c
         gt += t
     return gc, gt

@@ -141,6 +141,62 @@ static void or_sphere_update(const double *sphere, double dt, const double *x, d
     }
 }
 
+/* Reverse mode of or_sphere_update for a free node. Given the adjoints gy of the new position and
+   gw of the new velocity, returns gx (adjoint of x) and gv (adjoint of the velocity v before the
+   constraint). Outside the sphere y = x + dt v, v' = v. Inside, with u = x + dt v - c, r = |u|,
+   n = u / r, s = v . n and k = max(s, 0) - (1 - fric) s:
+     y = c + R n,   v' = (1 - fric) v + k n,
+   so by the chain rule
+     g_s = (gw . n)([s > 0] - (1 - fric)),   g_n = R gy + k gw + g_s v,
+     gv = (1 - fric) gw + g_s n + dt g_u,   gx = g_u = (g_n - (n . g_n) n) / r
+   (dn/du = (I - n n^T) / r; n is the constant (0, 0, 1) at r = 0, where g_u = 0). */
+static void or_sphere_adjoint(const double *sphere, double dt, const double *x, const double *v,
+                              const double *gy, const double *gw, double *gx, double *gv)
+{
+    for (int a = 0; a < 3; ++a) { gx[a] = gy[a]; gv[a] = gw[a] + dt * gy[a]; }
+    if (!sphere || !(sphere[3] > 0.0)) return;
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = x[a] + dt * v[a] - sphere[a];
+    const double r = sqrt(or_dot3(d, d));
+    if (!(r < sphere[3])) return;
+    double nn[3] = {0.0, 0.0, 1.0};
+    if (r > 0.0)
+        for (int a = 0; a < 3; ++a) nn[a] = d[a] / r;
+    const double kf = 1.0 - sphere[4];
+    const double s = or_dot3(v, nn);
+    const double k = (s > 0.0 ? s : 0.0) - kf * s;
+    const double gs = or_dot3(gw, nn) * ((s > 0.0 ? 1.0 : 0.0) - kf);
+    double gn[3], gu[3];
+    for (int a = 0; a < 3; ++a) gn[a] = sphere[3] * gy[a] + k * gw[a] + gs * v[a];
+    const double ngn = or_dot3(nn, gn);
+    for (int a = 0; a < 3; ++a) gu[a] = r > 0.0 ? (gn[a] - ngn * nn[a]) / r : 0.0;
+    for (int a = 0; a < 3; ++a) {
+        gx[a] = gu[a];
+        gv[a] = kf * gw[a] + gs * nn[a] + dt * gu[a];
+    }
+}
+
+/* Adjoint of eq. (5) at node p with the constraint: from g_next at p, adds dLoss/dx^k to the
+   position rows of g_cur and returns in gdv the adjoint of the velocity before the constraint
+   (v = v^k + dv + external terms; zero for a pinned node, whose v' = 0 and x' = x). v is that
+   velocity (needed only with a sphere). */
+static void or_store_node_adjoint(long n, long p, int pinned, double dt, const double *s, const double *v,
+                                  const double *sphere, const double *g_next, double *g_cur, double *gdv)
+{
+    double x[3], gy[3], gw[3], gx[3];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = s[a * n + p];
+        gy[a] = g_next[a * n + p];
+        gw[a] = g_next[(3 + a) * n + p];
+    }
+    if (pinned) {
+        for (int a = 0; a < 3; ++a) { gx[a] = gy[a]; gdv[a] = 0.0; }
+    } else {
+        or_sphere_adjoint(sphere, dt, x, v, gy, gw, gx, gdv);
+    }
+    for (int a = 0; a < 3; ++a) g_cur[a * n + p] += gx[a];
+}
+
 /* Writes node p of eq. (5): velocity v' (zero when pinned) and position, with the sphere. */
 static void or_store_node(long n, long p, int pinned, double dt, const double *s, double *v,
                           const double *sphere, double *out)
@@ -451,9 +507,10 @@ static void or_pressure_adjoint(int H, int W, const double *s, int i, int j, dou
 
 /* Reverse mode of or_cnn_forward (emu = 0). Given g_next = dLoss/dS^{k+1}, accumulate
    dLoss/dS^k into g_cur, dLoss/dS^{k-1} into g_prev and dLoss/dtheta into g_theta. */
-void or_cnn_backward(int H, int W, int ch, double alpha, double dt, double pm, const uint8_t *pin,
-                     const double *theta, const double *s_prev, const double *s_cur,
-                     const double *g_next, double *g_cur, double *g_prev, double *g_theta)
+void or_cnn_backward(int H, int W, int ch, double alpha, double dt, const double *a_ext, double pm,
+                     const uint8_t *pin, const double *theta, const double *s_prev, const double *s_cur,
+                     const double *g_next, double *g_cur, double *g_prev, double *g_theta,
+                     const double *sphere)
 {
     const long n = (long)H * W;
     const or_layout Lo = or_theta_layout(ch);
@@ -464,13 +521,15 @@ void or_cnn_backward(int H, int W, int ch, double alpha, double dt, double pm, c
         for (int j = 0; j < W; ++j) {
             const long p = (long)i * W + j;
             or_cell_node(H, W, ch, alpha, theta, &Lo, s_cur, dS, i, j, 0, o);
-            /* eq. (5): x' = x + dt v', v' = (1 - pin)(v + dv + dt a) */
-            for (int a = 0; a < 3; ++a) {
-                const double gvt = g_next[(3 + a) * n + p] + dt * g_next[a * n + p];
-                g_cur[a * n + p] += g_next[a * n + p];
-                gdv[a] = pin[p] ? 0.0 : gvt;
-                g_cur[(3 + a) * n + p] += gdv[a];
+            /* eq. (5): x' = x + dt v', v' = C(v + dv + dt a + pressure), C = pins and sphere */
+            double v[3] = {0.0, 0.0, 0.0};
+            if (sphere) {
+                double fp[3] = {0.0, 0.0, 0.0};
+                if (pm != 0.0) or_pressure(H, W, s_cur, i, j, dt * pm, fp);
+                for (int a = 0; a < 3; ++a) v[a] = s_cur[(3 + a) * n + p] + o->dv[a] + dt * a_ext[a] + fp[a];
             }
+            or_store_node_adjoint(n, p, pin[p], dt, s_cur, v, sphere, g_next, g_cur, gdv);
+            for (int a = 0; a < 3; ++a) g_cur[(3 + a) * n + p] += gdv[a];
             if (pm != 0.0) or_pressure_adjoint(H, W, s_cur, i, j, dt * pm, gdv, g_cur);
             /* eq. (7) heads */
             for (int c = 0; c < ch; ++c) { gphi[c] = 0.0; gnn[c] = 0.0; gdd[c] = 0.0; }
@@ -582,19 +641,23 @@ void or_pair_forward(int H, int W, double alpha, double dt, const double *a_ext,
 
 /* Reverse mode of or_pair_forward: g_next = dLoss/dS^{k+1} gives dLoss/dS^k (into g_cur) and
    dLoss/dtheta (into g_theta). */
-void or_pair_backward(int H, int W, double alpha, double dt, double pm, const uint8_t *pin,
-                      const double *theta, const double *s_cur, const double *g_next, double *g_cur,
-                      double *g_theta)
+void or_pair_backward(int H, int W, double alpha, double dt, const double *a_ext, double pm,
+                      const uint8_t *pin, const double *theta, const double *s_cur, const double *g_next,
+                      double *g_cur, double *g_theta, const double *sphere)
 {
     const long n = (long)H * W;
     for (int i = 0; i < H; ++i)
         for (int j = 0; j < W; ++j) {
             const long p = (long)i * W + j;
-            double gdv[3];
+            double gdv[3], v[3] = {0.0, 0.0, 0.0};
+            if (sphere) {  /* the velocity before the constraint, as in or_pair_forward */
+                double dv[3], fp[3] = {0.0, 0.0, 0.0};
+                or_pair_node(H, W, alpha, theta, s_cur, i, j, dv);
+                if (pm != 0.0) or_pressure(H, W, s_cur, i, j, dt * pm, fp);
+                for (int a = 0; a < 3; ++a) v[a] = s_cur[(3 + a) * n + p] + dv[a] + dt * a_ext[a] + fp[a];
+            }
+            or_store_node_adjoint(n, p, pin[p], dt, s_cur, v, sphere, g_next, g_cur, gdv);
             for (int a = 0; a < 3; ++a) {
-                const double gvt = g_next[(3 + a) * n + p] + dt * g_next[a * n + p];
-                g_cur[a * n + p] += g_next[a * n + p];
-                gdv[a] = pin[p] ? 0.0 : gvt;
                 g_cur[(3 + a) * n + p] += gdv[a];
                 g_theta[OR_PBL + a] += gdv[a];
             }

@@ -126,3 +126,130 @@ def test_frames_apply_the_same_constraint():
     np.testing.assert_allclose(conv, ref, rtol=0, atol=1e-15)
     np.testing.assert_allclose(pair, ref, rtol=0, atol=1e-15)
     assert np.abs(ref - oracle.ms_step(H, W, 0.1, 1.0, np.zeros(3), pin, s, _no_springs(g=tuple(a), dt=dt))).max() > 1e-3
+
+
+# ------------------------------------------------------------------ reverse mode through C
+def _touching_frame(H, W, seed, h=0.05):
+    """A sheet in the plane z = 0 with z noise and velocities of both signs, over a sphere whose
+    top lies just under the middle: one frame sends some nodes inside, with inward and outward
+    normal velocity."""
+    s = np.zeros((6, H * W))
+    s[:3] = I.flat_grid(H, W, h)
+    s[2] = I.random_array((H * W,), seed=seed, scale=0.003)
+    s[3:] = I.random_array((3, H * W), seed=seed + 1, scale=1.0)
+    s0 = s.copy()
+    s0[3:] -= I.random_array((3, H * W), seed=seed + 2, scale=0.05)
+    s0[:3] -= 5e-3 * s[3:]
+    R = 1.0
+    sphere = [0.5 * (W - 1) * h, 0.5 * (H - 1) * h, -R + 0.002, R, 0.3]
+    return s0, s, sphere
+
+
+def _inside_with_both_signs(s_cur, v_pre, pin, sphere, dt):
+    c, R = np.asarray(sphere[:3]), sphere[3]
+    y = s_cur[:3] + dt * v_pre
+    d = y - c[:, None]
+    r = np.linalg.norm(d, axis=0)
+    inside = (r < R) & (pin == 0)
+    sgn = np.sum(v_pre * d, axis=0)
+    return int(inside.sum()), int((inside & (sgn > 0)).sum()), int((inside & (sgn < 0)).sum())
+
+
+def _fd_check(loss, x, grad, idx, rel):
+    for k in idx:
+        e = rel * max(1.0, abs(x.flat[k]))
+        xp, xm = x.copy(), x.copy()
+        xp.flat[k] += e
+        xm.flat[k] -= e
+        fd = (loss(xp) - loss(xm)) / (2 * e)
+        assert abs(grad.flat[k] - fd) <= 1e-6 * max(1.0, np.abs(grad).max()), (k, grad.flat[k], fd)
+
+
+def test_conv_backward_through_the_sphere_finite_differences():
+    """Central differences of a random linear functional of one conv-cell frame with a sphere,
+    with respect to sampled parameters and state entries of both input states. Some nodes end
+    inside the sphere, moving inward and outward."""
+    H, W, ch, dt = 7, 8, 16, 5e-3
+    s0, s1, sphere = _touching_frame(H, W, 31)
+    pin = I.pin_mask(H, W, "two_top_corners")
+    a = np.array([0.4, -0.3, -9.8])
+    th = I.init_theta(ch, seed=32).astype(np.float64) * 4
+    tg = I.random_array((6, H * W), seed=33)
+    free, _ = oracle.cnn_forward(H, W, ch, 1.0, dt, a, pin, th, s0, s1)
+    n_in, n_out, n_inw = _inside_with_both_signs(s1, free[3:], pin, sphere, dt)
+    assert n_in >= 5 and n_out >= 1 and n_inw >= 1 and n_in <= H * W - 5, (n_in, n_out, n_inw)
+
+    def fwd(th_=th, s0_=s0, s1_=s1):
+        out, _ = oracle.cnn_forward(H, W, ch, 1.0, dt, a, pin, th_, s0_, s1_, sphere=sphere)
+        return float(np.sum(tg * out))
+
+    gc, gp, gt = oracle.cnn_backward(H, W, ch, 1.0, dt, pin, th, s0, s1, tg, a_ext=a, sphere=sphere)
+    rs = np.random.RandomState(5)
+    _fd_check(lambda t: fwd(th_=t), th, gt, rs.choice(th.size, 80, replace=False), 1e-6)
+    _fd_check(lambda s: fwd(s1_=s), s1, gc, rs.choice(s1.size, 80, replace=False), 1e-7)
+    _fd_check(lambda s: fwd(s0_=s), s0, gp, rs.choice(s0.size, 40, replace=False), 1e-7)
+    # without the sphere the same call is the plain reverse mode
+    gc2, _, gt2 = oracle.cnn_backward(H, W, ch, 1.0, dt, pin, th, s0, s1, tg)
+    assert np.abs(gt2 - gt).max() > 1e-3 * np.abs(gt).max()
+    gc3, _, gt3 = oracle.cnn_backward(H, W, ch, 1.0, dt, pin, th, s0, s1, tg, a_ext=a,
+                                      sphere=[*sphere[:3], 0.0, 0.3])
+    np.testing.assert_array_equal(gt3, gt2)
+    np.testing.assert_array_equal(gc3, gc2)
+
+
+def test_pair_backward_through_the_sphere_finite_differences():
+    """The same for the pair cell, with pressure on as well."""
+    H, W, dt, pm = 7, 8, 5e-3, 30.0
+    _, s1, sphere = _touching_frame(H, W, 41)
+    pin = I.pin_mask(H, W, "one_top_corner")
+    a = np.array([0.2, 0.1, -9.8])
+    th = I.random_array((51,), seed=42, scale=0.6)
+    th[:12] = 20.0 + I.random_array((12,), seed=43, scale=5.0)
+    tg = I.random_array((6, H * W), seed=44)
+    free, _ = oracle.pair_forward(H, W, 1.0, dt, a, pin, th, s1, pm=pm)
+    n_in, n_out, n_inw = _inside_with_both_signs(s1, free[3:], pin, sphere, dt)
+    assert n_in >= 5 and n_out >= 1 and n_inw >= 1 and n_in <= H * W - 5, (n_in, n_out, n_inw)
+
+    def fwd(th_=th, s_=s1):
+        out, _ = oracle.pair_forward(H, W, 1.0, dt, a, pin, th_, s_, pm=pm, sphere=sphere)
+        return float(np.sum(tg * out))
+
+    gc, gt = oracle.pair_backward(H, W, 1.0, dt, pin, th, s1, tg, pm=pm, a_ext=a, sphere=sphere)
+    rs = np.random.RandomState(6)
+    _fd_check(lambda t: fwd(th_=t), th, gt, range(51), 1e-6)
+    _fd_check(lambda s: fwd(s_=s), s1, gc, rs.choice(s1.size, 80, replace=False), 1e-7)
+
+
+def test_sphere_adjoint_is_the_transpose_of_the_tangent_map():
+    """One node, many random states inside the sphere: the reverse map's output paired with a
+    random direction equals the forward difference quotient along that direction (dot-product
+    test against the one-node frame of the simulator step with all forces off)."""
+    mat = _no_springs(g=(0.0, 0.0, 0.0), dt=0.05)
+    rs = np.random.RandomState(7)
+    c, R = np.array([0.1, -0.2, 0.3]), 1.0
+    H, W = 1, 2
+    checked = 0
+    for _ in range(40):
+        x = c + rs.uniform(-0.7, 0.7, 3)
+        v = rs.normal(size=3)
+        s = _two_nodes(x, v)
+        if not np.linalg.norm(x + mat.dt * v - c) < R - 1e-3:
+            continue
+        sph = [*c, R, 0.35]
+        g = rs.normal(size=(6, 2))
+        g[:, 1] = 0.0
+        # the pair cell with all weights zero is eq. (5) with the constraint alone
+        th = np.zeros(51)
+        gc, _ = oracle.pair_backward(H, W, 1.0, mat.dt, np.zeros(2, np.uint8), th, s, g, sphere=sph)
+        dirn = rs.normal(size=(6, 2))
+        dirn[:, 1] = 0.0
+        e = 1e-7
+        fp, _ = oracle.pair_forward(H, W, 1.0, mat.dt, np.zeros(3), np.zeros(2, np.uint8), th, s + e * dirn,
+                                    sphere=sph)
+        fm, _ = oracle.pair_forward(H, W, 1.0, mat.dt, np.zeros(3), np.zeros(2, np.uint8), th, s - e * dirn,
+                                    sphere=sph)
+        lhs = float(np.sum(g * (fp - fm)) / (2 * e))
+        rhs = float(np.sum(gc * dirn))
+        assert abs(lhs - rhs) <= 1e-6 * max(1.0, abs(rhs)), (lhs, rhs)
+        checked += 1
+    assert checked >= 10
