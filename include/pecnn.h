@@ -97,9 +97,10 @@ int pecnn_plan_set_pressure(pecnn_plan* plan, const float* pressure, void* strea
    sphere, the default of a new plan), friction f in [0, 1]. For a free node with velocity v'
    after the rest of eq. (5), y = x + dt v'; if |y - c| < R the node moves to c + R n,
    n = (y - c)/|y - c| (n = +z when y = c), the inward part of v'.n is removed and the
-   tangential part of v' is scaled by 1 - f. Applies to the mass-spring step and to every frame
-   (pecnn_forward, pecnn_rollout); pecnn_backward returns PECNN_E_UNSUPPORTED for a plan with a
-   sphere. Synchronous on `stream`; drops the rollout's cached graphs when the kernels change. */
+   tangential part of v' is scaled by 1 - f. Applies to the mass-spring step, to every frame
+   (pecnn_forward, pecnn_rollout) and to the reverse pass (pecnn_backward; set the spheres before
+   sizing its workspace, which grows by two states when a plan has one). Synchronous on `stream`;
+   drops the rollout's cached graphs when the kernels change. */
 int pecnn_plan_set_spheres(pecnn_plan* plan, const float* sphere, void* stream);
 
 /* ------------------------------------------------------------------ mass-spring step */
@@ -173,8 +174,12 @@ int pecnn_forward(const pecnn_plan* plan, const pecnn_model* model, const float*
    gradient backpropagation). g_next = dLoss/dS^{k+1} (device [6][N_total]). Accumulates (+=)
    dLoss/dS^k into g_cur, dLoss/dS^{k-1} into g_prev (both device [6][N_total], may be NULL to
    skip) and dLoss/dtheta into g_theta (device [theta size]). Activations are recomputed from
-   (s_prev, s_cur); no tape. Deterministic: fixed-order reductions.
-   ws: pecnn_workspace_bytes(plan, model, PECNN_WS_BACKWARD) bytes. */
+   (s_prev, s_cur); no tape. Deterministic: fixed-order reductions. With spheres in the plan the
+   frame is first recomputed without them (for the velocities before the constraint) and g_next
+   is carried back through each sphere's projection and friction (the constraint is piecewise
+   smooth: at its switching points, |y - c| = R and v.n = 0, the branch the forward took is
+   differentiated). ws: pecnn_workspace_bytes(plan, model, PECNN_WS_BACKWARD) bytes, queried
+   after the plan's spheres are set. */
 int pecnn_backward(const pecnn_plan* plan, const pecnn_model* model, const float* s_prev,
                    const float* s_cur, const float* g_next, float* g_cur, float* g_prev,
                    float* g_theta, void* ws, size_t ws_bytes, void* stream);

@@ -26,6 +26,8 @@ int pair_backward_launch(const pecnn_plan*, const pecnn_model*, const float*, co
                          hipStream_t);
 int backward_launch(const pecnn_plan*, const pecnn_model*, const float*, const float*, const float*, float*,
                     float*, float*, void*, hipStream_t);
+int sphere_adjoint_launch(const pecnn_plan*, float, const float*, const float*, const float*, float*, hipStream_t);
+int zero_floats_launch(float*, int64_t, hipStream_t);
 size_t reduce_ws_bytes(const pecnn_plan*);
 int reduce_launch(const pecnn_plan*, const MsParamsDev&, const float*, const float*, double*, void*, hipStream_t);
 int loss_launch(const pecnn_plan*, const float*, const float*, float, float, float, int64_t, double*, float*, void*,
@@ -482,6 +484,19 @@ int pecnn_plan_get_tiles(const pecnn_plan* p, int32_t* ms_cfg, int32_t* cnn_cfg)
   return PECNN_OK;
 }
 
+// Backward workspace: the reverse pass's own part, then, when some instance has a sphere, the
+// frame without spheres, the rewritten output adjoint and zeroed sphere records.
+static size_t backward_ws_base(const pecnn_plan* p, const pecnn_model* m) {
+  return align256(m->cell == PECNN_CELL_PAIR ? pair_backward_ws_bytes(p) : backward_ws_bytes(p, m->ch));
+}
+
+static size_t backward_ws_total(const pecnn_plan* p, const pecnn_model* m) {
+  size_t b = backward_ws_base(p, m);
+  if (p->has_sphere)
+    b += 2 * align256(6 * (size_t)p->total * sizeof(float)) + align256((size_t)p->n * kSphereStride * sizeof(float));
+  return b;
+}
+
 int pecnn_workspace_bytes(const pecnn_plan* p, const pecnn_model* m, int32_t which, size_t* bytes) {
   if (check_plan(p) || !bytes) { set_error("null plan or bytes"); return PECNN_E_INVALID; }
   switch (which) {
@@ -490,7 +505,7 @@ int pecnn_workspace_bytes(const pecnn_plan* p, const pecnn_model* m, int32_t whi
     case PECNN_WS_BACKWARD: {
       int rc = check_model(m);
       if (rc) return rc;
-      *bytes = align256(m->cell == PECNN_CELL_PAIR ? pair_backward_ws_bytes(p) : backward_ws_bytes(p, m->ch));
+      *bytes = backward_ws_total(p, m);
       return PECNN_OK;
     }
     case PECNN_WS_ROLLOUT: *bytes = rollout_layout(p, nullptr).bytes; return PECNN_OK;
@@ -535,14 +550,33 @@ int pecnn_backward(const pecnn_plan* p, const pecnn_model* m, const float* s_pre
   if (rc) return rc;
   if ((rc = check_model(m))) return rc;
   if (m->precision != PECNN_FP32) { set_error("backward needs an FP32 model"); return PECNN_E_UNSUPPORTED; }
-  if (p->has_sphere) { set_error("backward through the sphere constraint is not implemented"); return PECNN_E_UNSUPPORTED; }
   if (!s_prev || !s_cur || !g_next || !g_theta) { set_error("null state, gradient or theta gradient"); return PECNN_E_INVALID; }
   if (g_cur && g_prev && g_cur == g_prev) { set_error("g_cur and g_prev must differ"); return PECNN_E_INVALID; }
-  const size_t need = align256(m->cell == PECNN_CELL_PAIR ? pair_backward_ws_bytes(p) : backward_ws_bytes(p, m->ch));
+  const size_t need = backward_ws_total(p, m);
   if (!ws || ws_bytes < need) { set_error("backward workspace of %zu bytes needed", need); return PECNN_E_WORKSPACE; }
+  hipStream_t st = (hipStream_t)stream;
+  if (p->has_sphere) {
+    // The frame without spheres gives the velocities before the constraint; the sphere's
+    // reverse mode then rewrites g_next for the constraint-free reverse pass below.
+    const size_t sb = align256(6 * (size_t)p->total * sizeof(float));
+    char* e = (char*)ws + backward_ws_base(p, m);
+    float* vfree = (float*)e;
+    float* g_sph = (float*)(e + sb);
+    float* no_sphere = (float*)(e + 2 * sb);
+    rc = zero_floats_launch(no_sphere, (int64_t)p->n * kSphereStride, st);
+    if (rc) return rc;
+    pecnn_plan q = *p;
+    q.d_sphere = no_sphere;
+    q.has_sphere = 0;
+    rc = cnn_forward_launch(&q, q.cnn_cfg, m, s_prev, s_cur, vfree, nullptr, st);
+    if (rc) return rc;
+    rc = sphere_adjoint_launch(p, m->dt, s_cur, vfree, g_next, g_sph, st);
+    if (rc) return rc;
+    g_next = g_sph;
+  }
   if (m->cell == PECNN_CELL_PAIR)  // the pair cell does not read S^{k-1}: g_prev gets nothing
-    return pair_backward_launch(p, m, s_cur, g_next, g_cur, g_theta, ws, (hipStream_t)stream);
-  return backward_launch(p, m, s_prev, s_cur, g_next, g_cur, g_prev, g_theta, ws, (hipStream_t)stream);
+    return pair_backward_launch(p, m, s_cur, g_next, g_cur, g_theta, ws, st);
+  return backward_launch(p, m, s_prev, s_cur, g_next, g_cur, g_prev, g_theta, ws, st);
 }
 
 int cloth_reduce_fp64(const pecnn_plan* p, const cloth_ms_params* prm, const float* s, const float* s_ref, double* out,

@@ -649,6 +649,51 @@ int pair_backward_launch(const pecnn_plan* plan, const pecnn_model* m, const flo
   return PECNN_OK;
 }
 
+// ---------------------------------------------------------------- the sphere's reverse mode
+// One thread per node over the 256-node chunks: rewrites the frame's output adjoint so that the
+// constraint-free reverse pass that follows goes through each instance's sphere (sphere_adjoint).
+// vfree holds the frame computed without spheres: its velocity rows are the velocities before the
+// constraint.
+__global__ __launch_bounds__(256) void sphere_adjoint_kernel(
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+    int64_t N, const uint8_t* __restrict__ pin, const float* __restrict__ sc, const float* __restrict__ vfree,
+    const float* __restrict__ gn, const float* __restrict__ sphere, float dt, float* __restrict__ gt) {
+  const int t = blockIdx.x;
+  const int b = chunk_inst[t];
+  const InstDev I = inst[b];
+  const int local = (t - prefix[b]) * kChunk + (int)threadIdx.x;
+  if (local >= I.H * I.W) return;
+  const int64_t p = I.off + local;
+  float g[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) g[c] = gn[c * N + p];
+  if (pin[p] == 0)
+    sphere_adjoint(sphere + (int64_t)b * kSphereStride, dt, sc[p], sc[N + p], sc[2 * N + p], vfree[3 * N + p],
+                   vfree[4 * N + p], vfree[5 * N + p], g);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) gt[c * N + p] = g[c];
+}
+
+__global__ __launch_bounds__(256) void zero_floats_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+int sphere_adjoint_launch(const pecnn_plan* plan, float dt, const float* sc, const float* vfree, const float* gn,
+                          float* gt, hipStream_t st) {
+  hipLaunchKernelGGL(sphere_adjoint_kernel, dim3(plan->n_tiles[kCfgChunk]), dim3(256), 0, st, plan->d_inst,
+                     plan->d_prefix[kCfgChunk], plan->d_chunk_inst, plan->total, plan->pin, sc, vfree, gn,
+                     plan->d_sphere, dt, gt);
+  PECNN_LAUNCH_CHECK("sphere_adjoint_kernel");
+  return PECNN_OK;
+}
+
+int zero_floats_launch(float* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_floats_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  PECNN_LAUNCH_CHECK("zero_floats_kernel");
+  return PECNN_OK;
+}
+
 size_t backward_ws_bytes(const pecnn_plan* plan, int ch) {
   const BwdLayout L = bwd_layout(ch);
   const size_t fac = (size_t)fac_floats(plan->total, L.rows) * sizeof(float);

@@ -1,7 +1,8 @@
 """GPU parity with a sphere in the constraint of eq. (5) (pecnn_plan_set_spheres) against the FP64
 oracle: the mass-spring step and the three frames (bf16 and FP32 convolution cell, pair cell) on
 ragged and aligned batches where a cap of each cloth penetrates its sphere, every tile
-configuration bit for bit, the rollout, and the error paths.
+configuration bit for bit, the rollout, the reverse pass through the constraint (both cells, FP32)
+and the error paths.
 
 Whether a node is inside the sphere is decided in FP32 on the GPU and in FP64 in the oracle; nodes
 whose updated position lies within a small margin of the surface (1e-5 of the radius for FP32
@@ -170,12 +171,67 @@ def test_sphere_errors(L):
     th = I.init_theta(16, seed=1)
     model = L.make_model(dev_tensor(th), 16, L.PECNN_FP32, dt=5e-3)
     s = dev_tensor(batch.state)
-    with pytest.raises(L.PecnnError):  # no backward through the sphere constraint
-        L.pecnn_backward(plan, model, s, s, torch.zeros_like(s), None, None, torch.zeros(th.size, device="cuda"))
     with pytest.raises(L.PecnnError):
         plan.set_spheres([[0, 0, 0, 1.0, 1.5], [0, 0, 0, 1.0, 0.0]])   # friction above 1
     with pytest.raises(L.PecnnError):
         plan.set_spheres([[0, 0, 0, -1.0, 0.5], [0, 0, 0, 1.0, 0.0]])  # negative radius
-    plan.set_spheres(np.zeros((2, 5)))  # no spheres: the backward works again
+    plan.set_spheres(np.zeros((2, 5)))
+    small = plan.workspace(L.WS_BACKWARD, model)  # sized without spheres
+    plan.set_spheres(batch.sphere)
+    assert plan.workspace(L.WS_BACKWARD, model).numel() > small.numel()
+    with pytest.raises(L.PecnnError):  # the reverse pass through spheres needs the larger workspace
+        L.pecnn_backward(plan, model, s, s, torch.zeros_like(s), None, None, torch.zeros(th.size, device="cuda"),
+                         ws=small)
     L.pecnn_backward(plan, model, s, s, torch.zeros_like(s), None, None, torch.zeros(th.size, device="cuda"))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("cell", ["conv", "pair"])
+def test_backward_with_spheres_matches_oracle(L, cell):
+    """The reverse pass through each instance's sphere against the oracle's, FP32. The output
+    adjoint is zeroed at nodes the two sides might send down different branches of the
+    constraint: an updated position within 1e-5 R of the surface, or a normal velocity within
+    1e-4 of the speed of zero."""
+    import torch
+    batch, s0, s1, th = _frame_inputs(SIZE_SETS["aligned"]() + [(32, 32), (17, 23)], 940)
+    if cell == "pair":
+        th = I.init_pair_theta(seed=941).astype(np.float32)
+        ch, c = 12, L.CELL_PAIR
+        free, _ = oracle.batch_pair_forward(_plain(batch), 1.0, 5e-3, th.astype(np.float64), s1)
+    else:
+        ch, c = 32, L.CELL_CONV
+        free, _ = oracle.batch_cnn_forward(_plain(batch), 32, 1.0, 5e-3, th.astype(np.float64), s0, s1)
+    margin = _margin(batch, free[:3])
+    vn = np.zeros(batch.total)
+    for b in range(batch.n):
+        if batch.sphere[b, 3] > 0:
+            sl = batch.instance(b)
+            d = free[:3, sl] - batch.sphere[b, :3].astype(np.float64)[:, None]
+            vn[sl] = np.sum(free[3:, sl] * d, axis=0) / np.maximum(np.linalg.norm(d, axis=0), 1e-30)
+    speed = np.linalg.norm(free[3:], axis=0)
+    unsure = (np.abs(margin) <= 1e-5 * 0.3) | ((margin < 0) & (np.abs(vn) <= 1e-4 * speed))
+    inside = (margin < 0) & (batch.pin == 0) & ~unsure
+    assert inside.sum() >= 20 and unsure.sum() <= 0.05 * inside.sum(), (inside.sum(), unsure.sum())
+    gn = I.random_array((6, batch.total), seed=942)
+    gn[:, unsure] = 0.0
+    gn = gn.astype(np.float32)
+    plan = L.Plan.from_batch(batch)
+    model = L.make_model(dev_tensor(th.astype(np.float32)), ch, L.PECNN_FP32, dt=5e-3, cell=c)
+    gc = torch.zeros(6, batch.total, device="cuda")
+    gp = torch.zeros_like(gc)
+    gt = torch.zeros(th.size, device="cuda")
+    L.pecnn_backward(plan, model, dev_tensor(s0), dev_tensor(s1), dev_tensor(gn), gc, gp, gt)
+    torch.cuda.synchronize()
+    args64 = [a.astype(np.float64) for a in (th, s0, s1, gn)]
+    if cell == "pair":
+        rc, rt = oracle.batch_pair_backward(batch, 1.0, 5e-3, args64[0], args64[2], args64[3])
+        rp = np.zeros_like(rc)
+        rt0 = oracle.batch_pair_backward(_plain(batch), 1.0, 5e-3, args64[0], args64[2], args64[3])[1]
+    else:
+        rc, rp, rt = oracle.batch_cnn_backward(batch, 32, 1.0, 5e-3, *args64)
+        rt0 = oracle.batch_cnn_backward(_plain(batch), 32, 1.0, 5e-3, *args64)[2]
+    got_t = gt.cpu().numpy()
+    assert rel_inf(gc.cpu().numpy(), rc) <= 1e-4
+    assert rel_inf(gp.cpu().numpy(), rp) <= 1e-4
+    assert rel_inf(got_t, rt) <= 1e-4
+    assert rel_inf(got_t, rt0) > 1e-2  # the spheres matter to the gradient
