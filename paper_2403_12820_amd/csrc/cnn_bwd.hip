@@ -650,6 +650,45 @@ int pair_backward_launch(const pecnn_plan* plan, const pecnn_model* m, const flo
 }
 
 // ---------------------------------------------------------------- the sphere's reverse mode
+// Reverse mode of sphere_update for a free node, as a change of the frame's output adjoint.
+// Without the constraint, y = x + dt v and v' = v send (gy, gw) to gx = gy, gv = gw + dt gy.
+// Inside the sphere, with u = y - c, r = |u|, n = u / r, s = v . n, k = max(s, 0) - (1 - fric) s,
+// the step is y = c + R n, v' = (1 - fric) v + k n, whose chain rule gives
+//   g_s = (gw . n)([s > 0] - (1 - fric)),  g_n = R gy + k gw + g_s v,  g_u = (I - n n^T) g_n / r,
+//   gx = g_u,  gv = (1 - fric) gw + g_s n + dt g_u.
+// Replacing (gy, gw) by (g_u, (1 - fric) gw + g_s n) makes the constraint-free reverse pass give
+// exactly these. The inside test repeats the forward's FP32 arithmetic, so both take the same
+// branch. v is the velocity before the constraint; g holds (gy, gw) and is updated in place.
+__device__ __forceinline__ void sphere_adjoint(const float* __restrict__ sph, float dt, float x0, float x1, float x2,
+                                               float v0, float v1, float v2, float g[6]) {
+  const float R = sph[3];
+  if (!(R > 0.f)) return;
+  const float d0 = __builtin_fmaf(dt, v0, x0) - sph[0], d1 = __builtin_fmaf(dt, v1, x1) - sph[1],
+              d2 = __builtin_fmaf(dt, v2, x2) - sph[2];
+  const float r2 = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
+  if (!(r2 < R * R)) return;
+  float n0 = 0.f, n1 = 0.f, n2 = 1.f, ir = 0.f;  // at r = 0 the normal is constant: g_u = 0
+  if (r2 > 0.f) {
+    ir = 1.f / __builtin_sqrtf(r2);
+    n0 = d0 * ir;
+    n1 = d1 * ir;
+    n2 = d2 * ir;
+  }
+  const float vn = __builtin_fmaf(v2, n2, __builtin_fmaf(v1, n1, v0 * n0));
+  const float kf = 1.f - sph[4];
+  const float k = (vn > 0.f ? vn : 0.f) - kf * vn;
+  const float gs = (g[3] * n0 + g[4] * n1 + g[5] * n2) * ((vn > 0.f ? 1.f : 0.f) - kf);
+  const float gn0 = R * g[0] + k * g[3] + gs * v0, gn1 = R * g[1] + k * g[4] + gs * v1,
+              gn2 = R * g[2] + k * g[5] + gs * v2;
+  const float ngn = n0 * gn0 + n1 * gn1 + n2 * gn2;
+  g[0] = (gn0 - ngn * n0) * ir;
+  g[1] = (gn1 - ngn * n1) * ir;
+  g[2] = (gn2 - ngn * n2) * ir;
+  g[3] = kf * g[3] + gs * n0;
+  g[4] = kf * g[4] + gs * n1;
+  g[5] = kf * g[5] + gs * n2;
+}
+
 // One thread per node over the 256-node chunks: rewrites the frame's output adjoint so that the
 // constraint-free reverse pass that follows goes through each instance's sphere (sphere_adjoint).
 // vfree holds the frame computed without spheres: its velocity rows are the velocities before the
