@@ -70,3 +70,44 @@ def test_null_arguments_rejected_without_device():
     assert lib.pecnn_forward(None, None, None, None, None, None) == -1
     assert lib.pecnn_adam_step(0, 1e-3, 0.9, 0.999, 1e-8, 1, None, None, None, None, None) == -1
     assert lib.pecnn_gather_windows(None, 1, 1, None, 1, None, None, 1, 1, 1, None, None) == -1
+
+
+def _c_layout(tmp_path, structs):
+    """sizeof and every field's offset of the header's structs, as gcc lays them out."""
+    import subprocess
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "%s"' % HDR, "int main(void) {"]
+    for cname, fields in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in fields:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    """The binding's ctypes mirrors of the argument structs have the fields, offsets and sizes the
+    C compiler gives the header's declarations."""
+    pairs = {"pecnn_batch_desc": L.BatchDesc, "cloth_ms_params": L.MsParams, "pecnn_model": L.Model,
+             "pecnn_guard": L.Guard}
+    txt = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    structs = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", txt, flags=re.S):
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if decl:
+                for part in decl.split(","):
+                    names.append(re.sub(r"\[.*\]", "", part).replace("*", " ").split()[-1])
+        structs[name] = names
+    assert set(pairs) == set(structs), sorted(structs)
+    lay = _c_layout(tmp_path, structs)
+    for cname, cls in pairs.items():
+        assert [f[0] for f in cls._fields_] == structs[cname], cname
+        assert C.sizeof(cls) == lay[(cname, "size")], cname
+        for f in structs[cname]:
+            assert getattr(cls, f).offset == lay[(cname, f)], (cname, f)
