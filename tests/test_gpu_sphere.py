@@ -186,14 +186,23 @@ def test_sphere_errors(L):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("cell", ["conv", "pair"])
-def test_backward_with_spheres_matches_oracle(L, cell):
-    """The reverse pass through each instance's sphere against the oracle's, FP32. The output
-    adjoint is zeroed at nodes the two sides might send down different branches of the
-    constraint: an updated position within 1e-5 R of the surface, or a normal velocity within
-    1e-4 of the speed of zero."""
+def _sphere_pressures(n):
+    """Zero on every third instance, otherwise +-20 or +-40 N/m^2."""
+    return np.array([0.0 if b % 3 == 0 else 20.0 * (1 + b % 2) * (1 if b % 4 < 2 else -1) for b in range(n)],
+                    np.float32)
+
+
+@pytest.mark.parametrize("cell,pressure", [("conv", False), ("pair", False), ("conv", True), ("pair", True)])
+def test_backward_with_spheres_matches_oracle(L, cell, pressure):
+    """The reverse pass through each instance's sphere against the oracle's, FP32, without and
+    with the pressure of eq. (3) on some instances (the frame recomputed without spheres then
+    takes the kernels' pressure variant). The output adjoint is zeroed at nodes the two sides
+    might send down different branches of the constraint: an updated position within 1e-5 R of
+    the surface, or a normal velocity within 1e-4 of the speed of zero."""
     import torch
     batch, s0, s1, th = _frame_inputs(SIZE_SETS["aligned"]() + [(32, 32), (17, 23)], 940)
+    if pressure:
+        batch.pressure = _sphere_pressures(batch.n)
     if cell == "pair":
         th = I.init_pair_theta(seed=941).astype(np.float32)
         ch, c = 12, L.CELL_PAIR
