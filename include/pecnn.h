@@ -197,9 +197,10 @@ int pecnn_backward(const pecnn_plan* plan, const pecnn_model* model, const float
    compared): the last network step of the chunk is compared with 'substeps' mass-spring steps
    from the same input state, and an instance whose position RMS over its nodes, divided by its
    width (W-1) h, exceeds frame_err_max falls back. That costs
-   'substeps' mass-spring steps of the whole batch per check. The frame that tripped a test is
-   kept; the fall-back starts with the next one. frame_err_max <= 0 disables the test; NaN is
-   an error. */
+   'substeps' mass-spring steps of the whole batch per check. With the test on, an instance
+   that falls back at a check (by any of the three tests) takes the simulator's answer for that
+   frame in place of the network's; with it off, the frame that tripped is kept. The fall-back
+   starts with the next frame. frame_err_max <= 0 disables the test; NaN is an error. */
 typedef struct {
   float stretch_max;
   float energy_gain_max;

@@ -143,7 +143,8 @@ __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restr
                                                     const double* __restrict__ eref,
                                                     const double* __restrict__ escale, pecnn_guard G, int init,
                                                     int32_t* __restrict__ fallback, uint8_t* __restrict__ active_ms,
-                                                    double* __restrict__ stats, int* __restrict__ count) {
+                                                    uint8_t* __restrict__ tripped, double* __restrict__ stats,
+                                                    int* __restrict__ count) {
   __shared__ int sh[256];
   const int chk = init ? 0 : count[1] + 1;
   const int step = chk * G.check_every;
@@ -152,6 +153,7 @@ __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restr
   int cnt = 0;
   for (int b = threadIdx.x; b < n; b += 256) {
     const double e = now[4 * b + 1], st = now[4 * b + 2];
+    tripped[b] = 0;
     if (init) {
       e0[b] = e;
       stats[4 * b + 0] = e;
@@ -162,6 +164,7 @@ __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restr
                 (isfinite(eref[b]) && !((e - e0[b]) / eref[b] <= (double)G.energy_gain_max)) ||
                 (ferr && !(now[4 * b] * escale[b] <= ferr2)))) {
       fallback[b] = 1;
+      tripped[b] = 1;
       stats[4 * b + 3] = step;
     }
     stats[4 * b + 1] = e;
@@ -181,6 +184,24 @@ __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restr
   }
 }
 
+// Copies the six state planes of every instance flagged in 'tripped' from src to dst (one
+// thread per node over the 256-node chunks).
+__global__ __launch_bounds__(256) void take_tripped_kernel(const InstDev* __restrict__ inst,
+                                                           const int32_t* __restrict__ prefix,
+                                                           const int32_t* __restrict__ chunk_inst, int64_t N,
+                                                           const uint8_t* __restrict__ tripped,
+                                                           const float* __restrict__ src, float* __restrict__ dst) {
+  const int t = blockIdx.x;
+  const int b = chunk_inst[t];
+  if (!tripped[b]) return;
+  const InstDev I = inst[b];
+  const int local = (t - prefix[b]) * kChunk + (int)threadIdx.x;
+  if (local >= I.H * I.W) return;
+  const int64_t p = I.off + local;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) dst[c * N + p] = src[c * N + p];
+}
+
 struct RolloutWs {
   float* X;        // third rotating state
   float* T;        // mass-spring substep temporary
@@ -191,6 +212,7 @@ struct RolloutWs {
   double* escale;  // [n] 1 / (nodes width^2) for the frame-error test
   double* stats;   // [4n] used when the caller passes NULL
   uint8_t* active; // [n]
+  uint8_t* tripped; // [n] fell back at the current check
   int* count;      // [1]
   size_t bytes;
 };
@@ -209,6 +231,7 @@ static RolloutWs rollout_layout(const pecnn_plan* plan, void* base) {
   w.escale = (double*)(p + o); o += align256((size_t)plan->n * sizeof(double));
   w.stats = (double*)(p + o); o += align256(4 * (size_t)plan->n * sizeof(double));
   w.active = (uint8_t*)(p + o); o += align256((size_t)plan->n);
+  w.tripped = (uint8_t*)(p + o); o += align256((size_t)plan->n);
   w.count = (int*)(p + o); o += 256;
   w.bytes = o;
   return w;
@@ -657,8 +680,13 @@ static int record_chunk(pecnn_plan* p, const pecnn_model* m, const MsParamsDev& 
     int rc = reduce_launch(p, sim, C, ferr ? X : nullptr, w.now, w.part, st);
     if (rc) return rc;
     hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 0,
-                       fallback, w.active, stats, w.count);
+                       fallback, w.active, w.tripped, stats, w.count);
     PECNN_LAUNCH_CHECK("guard_kernel");
+    if (ferr) {  // an instance that fell back here takes the simulator's frame instead of the network's
+      hipLaunchKernelGGL(take_tripped_kernel, dim3(p->n_tiles[kCfgChunk]), dim3(256), 0, st, p->d_inst,
+                         p->d_prefix[kCfgChunk], p->d_chunk_inst, p->total, w.tripped, X, C);
+      PECNN_LAUNCH_CHECK("take_tripped_kernel");
+    }
   }
   return PECNN_OK;
 }
@@ -715,7 +743,7 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     rc = reduce_launch(p, sim, s_cur, nullptr, w.now, w.part, st);
     if (rc) return rc;
     hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 1,
-                       fallback, w.active, stats_d, w.count);
+                       fallback, w.active, w.tripped, stats_d, w.count);
     PECNN_LAUNCH_CHECK("guard_kernel");
     PECNN_HIP(hipMemcpyAsync(gc->host_count, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
     PECNN_HIP(hipStreamSynchronize(st));

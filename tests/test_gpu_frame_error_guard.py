@@ -3,17 +3,18 @@ term of eq. (8)).
 
 At a check, the last network frame is compared with 'substeps' mass-spring steps from the same
 input state; an instance whose position RMS over its nodes, divided by its width (W - 1) h,
-exceeds the bound falls back from the next frame on.
+exceeds the bound falls back. That frame itself is replaced by the simulator's answer, which
+the test has just computed.
 
 * One frame, one check: the oracle computes each instance's error (the FP64 cell of eq. (6)-(7)
   or the pair cell, and the FP64 simulator of eq. (1)-(5)). For every bound placed between two
   neighbouring errors at least 1.3x apart, the flags must be exactly the instances above it.
-  The margin covers the FP32 and bf16 rounding of the network. The frame that tripped is kept,
-  bit for bit.
+  The margin covers the FP32 and bf16 rounding of the network. The instances below the bound
+  keep the network's frame and the others hold the simulator's, bit for bit.
 * A bound no error reaches changes nothing: the rollout equals the plain frame loop bit for bit,
   so the simulator's answer went into the rotating buffer that holds nothing live.
 * A bound every error exceeds sends every instance to the simulator at the first check. The
-  rollout then equals 'every' network frames followed by plain mass-spring steps.
+  rollout then equals 'every' - 1 network frames followed by plain mass-spring steps.
 * A NaN bound is an argument error."""
 import numpy as np
 import pytest
@@ -97,6 +98,10 @@ def test_frame_error_flags_match_the_oracle(L, cell, prec):
     L.pecnn_forward(plan, model, dev_tensor(s0), dev_tensor(s1), one)
     torch.cuda.synchronize()
     one = one.cpu().numpy()
+    ms = torch.zeros(6, batch.total, device="cuda")
+    L.cloth_ms_step(plan, L.ms_params(MAT), dev_tensor(s1), ms, SUB)
+    torch.cuda.synchronize()
+    ms = ms.cpu().numpy()
     for bound in _bounds(err):
         a, b = dev_tensor(s0), dev_tensor(s1)
         fb = torch.zeros(batch.n, dtype=torch.int32, device="cuda")
@@ -107,7 +112,11 @@ def test_frame_error_flags_match_the_oracle(L, cell, prec):
         np.testing.assert_array_equal(fb.cpu().numpy() != 0, want, err_msg="bound %g, errors %s" % (bound, err))
         st = stats.cpu().numpy().reshape(-1, 4)
         np.testing.assert_array_equal(st[:, 3], np.where(want, 1.0, -1.0))
-        assert np.array_equal(b.cpu().numpy(), one) and np.array_equal(a.cpu().numpy(), s1)
+        got = b.cpu().numpy()
+        for i in range(batch.n):
+            sl = batch.instance(i)
+            assert np.array_equal(got[:, sl], (ms if want[i] else one)[:, sl]), (bound, i)
+        assert np.array_equal(a.cpu().numpy(), s1)
 
 
 def _frame_loop(L, plan, model, s0, s1, n):
@@ -140,7 +149,7 @@ def test_frame_error_bound_extremes(L, prec):
         torch.cuda.synchronize()
         assert np.all(fb.cpu().numpy() == 0)
         assert np.array_equal(a.cpu().numpy(), rp) and np.array_equal(b.cpu().numpy(), rc)
-    # everything trips at the first check: 'every' frames, then mass-spring steps
+    # everything trips at the first check: 'every' - 1 frames, then mass-spring steps
     a, b = dev_tensor(s0), dev_tensor(s1)
     fb = torch.zeros(batch.n, dtype=torch.int32, device="cuda")
     stats = torch.zeros(4 * batch.n, dtype=torch.float64, device="cuda")
@@ -148,10 +157,10 @@ def test_frame_error_bound_extremes(L, prec):
     torch.cuda.synchronize()
     assert np.all(fb.cpu().numpy() == 1)
     assert np.all(stats.cpu().numpy().reshape(-1, 4)[:, 3] == every)
-    _, cur = _frame_loop(L, plan, model, s0, s1, every)
+    _, cur = _frame_loop(L, plan, model, s0, s1, every - 1)
     cur = dev_tensor(cur)
     prev = None
-    for _ in range(n - every):
+    for _ in range(n - every + 1):
         nxt = torch.zeros_like(cur)
         L.cloth_ms_step(plan, sim, cur, nxt, SUB)
         prev, cur = cur, nxt
