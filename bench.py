@@ -14,7 +14,14 @@ Printed (one JSON line): the contract fields, plus
                   traffic (measured HBM bytes per launch) from the committed rocprofv3 counter
                   summary when it was taken on the current kernel source, else null;
   cpu_baseline  - the FP64 oracle's CNN frame on a bounded sample, single thread;
-  config        - the workload, raw frame rate, mass-spring rate, RMS and fallbacks.
+  config        - the workload, raw frame rate, mass-spring rate, RMS and fallbacks, and an
+                  untimed accuracy leg: RMS after --acc-frames network frames (default 100, the
+                  horizon of the accuracy target) under the same guard, against the FP32
+                  simulator over the same simulated time; rms_within_bound is decided there.
+
+Before the timed region the graphs of the rollout are captured by an untimed run of the same
+length (the library caches one graph per chunk length, buffer rotation and fall-back mix).
+--profile KIND launches one kernel a fixed number of times instead (for counter runs).
 
 --cell pair runs section 3.2's own cell read literally instead (twelve frozen
 neighbour-difference channels, FP32, on the mass-spring step's tiles) with its trained weights;
@@ -168,6 +175,61 @@ def cpu_suite(cores, budget_s=4.0):
     return {"cpu_suite": rows, "host_cpu": cpu, "nproc": os.cpu_count(), "kind": "oracle"}
 
 
+def profile_launches(kind, reps, instances=128, size=256, ch=32):
+    """Fixed launches of one kernel on the benchmark batch, for rocprofv3 counter runs (a counter
+    pass replays each dispatch, so the run is kept to the kernel of interest):
+      cnn    - the bf16 frame (Ch = 32, weights N(0, 0.02) seed 1), 128 cloths of 256 x 256;
+      ms     - the FP32 mass-spring step on the same batch;
+      bwd    - the FP32 reverse pass of the frame on 32 cloths of 64 x 64 (a training minibatch);
+      reduce - the FP64 diagnostics of the rollout guard;
+      copy   - a plain 1 GiB device copy, which calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    from paper_2403_12820_amd import _lib as L
+    from paper_2403_12820_amd import inputs as I
+    dev = torch.device("cuda:0")
+    if kind == "copy":
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": kind, "launches": reps, "bytes_read": src.numel() * 4,
+                          "bytes_written": dst.numel() * 4}))
+        return
+    mat = I.Material()
+    if kind == "bwd":
+        instances, size = 32, 64
+    batch = I.make_batch(I.random_scenes([(size, size)] * instances, seed=5))
+    plan = L.Plan.from_batch(batch, dev)
+    s0 = torch.tensor(batch.state, device=dev)
+    bufs = [s0.clone(), s0.clone(), torch.empty_like(s0)]
+    theta = torch.tensor(I.init_theta(ch, seed=1), device=dev)
+    if kind == "cnn":
+        model = L.make_model(theta, ch, L.PECNN_BF16, dt=10 * mat.dt)
+        for i in range(reps):
+            L.pecnn_forward(plan, model, bufs[i % 3], bufs[(i + 1) % 3], bufs[(i + 2) % 3])
+    elif kind == "ms":
+        sim = L.ms_params(mat)
+        for i in range(reps):
+            L.cloth_ms_step(plan, sim, bufs[i % 2], bufs[(i + 1) % 2], 1)
+    elif kind == "bwd":
+        model = L.make_model(theta, ch, L.PECNN_FP32, dt=10 * mat.dt)
+        g = torch.tensor(I.random_array((6, batch.total), seed=9).astype(np.float32), device=dev)
+        gc, gp = torch.zeros_like(s0), torch.zeros_like(s0)
+        gt = torch.zeros(theta.numel(), device=dev)
+        ws = plan.workspace(L.WS_BACKWARD, model)
+        for i in range(reps):
+            L.pecnn_backward(plan, model, bufs[0], bufs[1], g, gc, gp, gt, ws=ws)
+    elif kind == "reduce":
+        sim = L.ms_params(mat)
+        out = torch.empty(4 * batch.n, dtype=torch.float64, device=dev)
+        for i in range(reps):
+            L.cloth_reduce_fp64(plan, sim, bufs[0], bufs[1], out)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": kind, "launches": reps, "nodes": batch.total}))
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +247,8 @@ def main():
     ap.add_argument("--frame-err-max", type=float, default=0.0,
                     help="bound of the guard's frame-error test (RMS / width of one frame against the "
                          "simulator); 0 = off")
+    ap.add_argument("--acc-frames", type=int, default=100,
+                    help="network frames of the untimed accuracy leg (the RMS target's horizon)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -195,6 +259,9 @@ def main():
     ap.add_argument("--weights", default=None, help="a .npy of the cell's parameters (default: the committed ones)")
     ap.add_argument("--cell", choices=("conv", "pair"), default="conv",
                     help="conv: the bf16 convolution cell (default); pair: the paper's own cell, FP32")
+    ap.add_argument("--profile", choices=("cnn", "ms", "bwd", "reduce", "copy"), default=None,
+                    help="only fixed launches of one kernel (for rocprofv3 counter runs), then exit")
+    ap.add_argument("--profile-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (cloths would shard "
@@ -202,6 +269,9 @@ def main():
         sys.exit(2)
     if args.cpu_suite:
         print(json.dumps(cpu_suite(max(1, args.cpu_cores))))
+        return
+    if args.profile:
+        profile_launches(args.profile, args.profile_reps)
         return
 
     pair = args.cell == "pair"
@@ -250,15 +320,21 @@ def main():
     stats = torch.zeros(4 * batch.n, dtype=torch.float64, device=dev)
     ws = plan.workspace(L.WS_ROLLOUT)
 
-    # ---- timed region: K network frames of the batch
-    a.copy_(s0)
-    b.copy_(s0)
-    L.pecnn_rollout(plan, model, sim, guard, a, b, args.warmup, fb, stats, ws)
-    torch.cuda.synchronize()
+    # ---- untimed: W warm-up frames, then one rollout of the timed length from the same state, so
+    # that every graph the timed call replays (one per chunk length, buffer rotation and fall-back
+    # mix) is captured and instantiated before the clock starts
+    for frames in (args.warmup, args.steps):
+        a.copy_(s0)
+        b.copy_(s0)
+        fb.zero_()
+        L.pecnn_rollout(plan, model, sim, guard, a, b, frames, fb, stats, ws)
+        torch.cuda.synchronize()
     a.copy_(s0)
     b.copy_(s0)
     fb.zero_()
     torch.cuda.synchronize()
+
+    # ---- timed region: K network frames of the batch
     t0 = time.perf_counter()
     L.pecnn_rollout(plan, model, sim, guard, a, b, args.steps, fb, stats, ws)
     torch.cuda.synchronize()
@@ -279,11 +355,37 @@ def main():
 
     # ---- position RMS of the network rollout against the FP32 simulator, FP64 reduction
     red = torch.zeros(4 * batch.n, dtype=torch.float64, device=dev)
-    L.cloth_reduce_fp64(plan, sim, b, y, red)
-    torch.cuda.synchronize()
-    r = red.cpu().numpy().reshape(-1, 4)
     width = (batch.W - 1) * batch.h
-    rms = np.sqrt(r[:, 0] / (batch.H * batch.W)) / width
+
+    def rms_of(net, ref):
+        L.cloth_reduce_fp64(plan, sim, net, ref, red)
+        torch.cuda.synchronize()
+        r = red.cpu().numpy().reshape(-1, 4)
+        return np.sqrt(r[:, 0] / (batch.H * batch.W)) / width
+
+    rms = rms_of(b, y)
+
+    # ---- accuracy at the target's horizon (untimed region): H network frames (default 100, i.e.
+    # 1000 simulator steps) under the same guard, against the FP32 simulator over the same
+    # simulated time; the rollout is run twice and the second run timed, for the guarded rate
+    # over the whole horizon (fall-backs included)
+    H_acc = args.acc_frames
+    fb_acc = torch.zeros_like(fb)
+    stats_acc = torch.zeros_like(stats)
+    for rep in range(2):
+        a.copy_(s0)
+        b.copy_(s0)
+        fb_acc.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.pecnn_rollout(plan, model, sim, guard, a, b, H_acc, fb_acc, stats_acc, ws)
+        torch.cuda.synchronize()
+        t_acc = time.perf_counter() - t0
+    x.copy_(s0)
+    L.cloth_ms_step(plan, sim, x, y, H_acc * stride, ws=ms_ws)
+    rms_acc = rms_of(b, y)
+    fb_acc_host = fb_acc.cpu().numpy() != 0
+    st_acc = stats_acc.cpu().numpy().reshape(-1, 4)
 
     # ---- dominant kernel alone, HIP events on the launch stream
     st = torch.cuda.current_stream()
@@ -331,7 +433,14 @@ def main():
             "cnn_vs_ms_raw": raw / ms_rate,
             "cnn_vs_ms_sim_equivalent": value / ms_rate,
             "rms_vs_fp32_ms_width_mean": float(rms.mean()), "rms_vs_fp32_ms_width_max": float(rms.max()),
-            "rms_bound": 1e-2, "rms_within_bound": bool(rms.max() <= 1e-2),
+            "accuracy_horizon_frames": H_acc,
+            "rms_at_horizon_width_mean": float(rms_acc.mean()), "rms_at_horizon_width_max": float(rms_acc.max()),
+            "rms_bound": 1e-2, "rms_within_bound": bool(rms_acc.max() <= 1e-2),
+            "fallback_instances_at_horizon": int(fb_acc_host.sum()),
+            "fallback_node_fraction_at_horizon": float(sum(int(batch.H[k]) * int(batch.W[k])
+                                                           for k in np.nonzero(fb_acc_host)[0])) / N,
+            "first_fallback_frame_at_horizon": (int(st_acc[fb_acc_host, 3].min()) if fb_acc_host.any() else None),
+            "guarded_rate_over_horizon_node_steps_per_s": N * H_acc * stride / t_acc,
             "guard": {"stretch_max": args.stretch_max, "energy_gain_max": args.energy_gain_max,
                       "check_every": args.check_every, "frame_err_max": args.frame_err_max},
             "fallback_instances": fell, "fallback_rate": fell / batch.n,

@@ -213,7 +213,9 @@ typedef struct {
    they hold S^{k+n-1}, S^{k+n}. fallback: device int32 [n], in/out; nonzero marks an instance
    that uses the mass-spring step (set by the guard; the caller may preset it). stats: device
    FP64 [n][4] or NULL: energy at the start, energy at the last check, largest structural
-   stretch seen at checks, network step of the fall-back (-1 if none).
+   stretch seen at checks, network step of the fall-back (-1 if none). At a check that trips an
+   instance with the frame-error test on, the energy and stretch recorded are those of the
+   network's frame that the check judged, before the simulator's frame replaces it.
    ws: pecnn_workspace_bytes(plan, model, PECNN_WS_ROLLOUT). The steps between checks run as
    one captured HIP graph (cached in the plan per buffer set). The host reads the fallback
    count at the start and after every check but the last, so the call synchronises 'stream'

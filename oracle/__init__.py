@@ -18,6 +18,9 @@ Paper passages followed (section / equation):
   loss_mse                   - eq. (8), data term
   adam                       - Table 1 (optimizer Adam)
   energy, max_stretch, rms   - diagnostics of the rollout (no paper formula)
+  bf16_round                 - the operand rounding of the emulated-bf16 forward: float32,
+                               then bfloat16 by round to nearest, ties to even (no paper
+                               formula: the precision of the inference path is a design choice)
 """
 from __future__ import annotations
 
@@ -71,6 +74,7 @@ def _load():
         _lib.or_loss_mse.argtypes = [l, p, l, d, d, d, p, p, p]
         _lib.or_loss_mse.restype = d
         _lib.or_adam.argtypes = [l, d, d, d, d, i, p, p, p, p]
+        _lib.or_bf16_array.argtypes = [l, p, p]
     return _lib
 
 
@@ -144,6 +148,15 @@ def max_stretch(H, W, h, s, fam_mask=1) -> float:
 def sq_pos_err(H, W, s, ref) -> float:
     s, ref = _f64(s).reshape(6, H * W), _f64(ref).reshape(6, H * W)
     return _load().or_sq_pos_err(H, W, _ptr(s), _ptr(ref))
+
+
+def bf16_round(x) -> np.ndarray:
+    """The operand rounding of the emulated-bf16 forward (emu flags of cnn_forward): each value
+    taken to float32, then to bfloat16 with round to nearest, ties to even."""
+    x = _f64(x)
+    y = np.empty_like(x)
+    _load().or_bf16_array(x.size, _ptr(x), _ptr(y))
+    return y
 
 
 def theta_size(ch) -> int:

@@ -333,7 +333,11 @@ long or_theta_size(int ch) { return or_theta_layout(ch).total; }
 
 static int or_clamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-/* bfloat16 round-to-nearest-even of a float value, returned as double. */
+/* bfloat16 round-to-nearest-even of a float value, returned as double. The operands of the
+   bf16 products are float32 values in the library, so the argument is first taken to float
+   (round to nearest); bfloat16 keeps the upper 16 bits of the float32 encoding, and the lower
+   16 are rounded away to nearest, ties to the even upper half (a carry may reach the exponent,
+   and past the largest finite value it gives infinity). Infinities and NaNs pass unchanged. */
 static double or_bf16(double x)
 {
     float f = (float)x;
@@ -344,6 +348,12 @@ static double or_bf16(double x)
     u &= 0xffff0000u;
     memcpy(&f, &u, 4);
     return (double)f;
+}
+
+/* The rounding above over an array, for the tests that pin it. */
+void or_bf16_array(long n, const double *x, double *y)
+{
+    for (long t = 0; t < n; ++t) y[t] = or_bf16(x[t]);
 }
 
 /* ISRU with parameter alpha (section 3.2): sigma(z) = z / sqrt(1 + alpha z^2). */

@@ -163,9 +163,9 @@ def test_backward_with_pressure_matches_oracle(L):
     args = (batch, ch, 1.0, 5e-3, th.astype(np.float64), s0.astype(np.float64), s1.astype(np.float64),
             gn.astype(np.float64))
     rc, rp, rt = oracle.batch_cnn_backward(*args)
-    assert rel_inf(gc.cpu().numpy(), rc) <= 1e-4
-    assert rel_inf(gp.cpu().numpy(), rp) <= 1e-4
-    assert rel_inf(gt.cpu().numpy(), rt) <= 1e-4
+    assert rel_inf(gc.cpu().numpy(), rc) <= 1e-5, rel_inf(gc.cpu().numpy(), rc)
+    assert rel_inf(gp.cpu().numpy(), rp) <= 1e-5, rel_inf(gp.cpu().numpy(), rp)
+    assert rel_inf(gt.cpu().numpy(), rt) <= 1e-5, rel_inf(gt.cpu().numpy(), rt)
     batch.pressure = None
     rc0, _, _ = oracle.batch_cnn_backward(*args)
     assert rel_inf(rc0[:3], rc[:3]) > 1e-3  # the pressure adjoint is exercised

@@ -89,7 +89,7 @@ def test_bptt_gradient_matches_oracle(L, unroll):
             og[t] += gp
         ogt += gt
     assert abs(loss.item() - lv) <= 1e-5 * abs(lv)
-    assert rel_inf(gth.cpu().numpy(), ogt) <= 1e-3, rel_inf(gth.cpu().numpy(), ogt)
+    assert rel_inf(gth.cpu().numpy(), ogt) <= 1e-5, rel_inf(gth.cpu().numpy(), ogt)
 
 
 @pytest.mark.parametrize("alpha", [0.0, 0.5, 1.0])
@@ -141,7 +141,7 @@ def test_trainer_gradient_with_physics_term_matches_oracle(L, alpha):
             og[t] += gp
         ogt += gt
     assert abs(loss - lv) <= 1e-5 * abs(lv), (loss, lv)
-    assert rel_inf(gth, ogt) <= 1e-3, rel_inf(gth, ogt)
+    assert rel_inf(gth, ogt) <= 1e-5, rel_inf(gth, ogt)
 
 
 def test_trainer_rejects_bad_alpha(L):
