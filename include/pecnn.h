@@ -13,7 +13,9 @@
  * plane c starts at c*N_total.
  *
  * Ownership: the caller allocates and frees every buffer (state, gradients, parameters,
- * workspaces, plan memory). The library never allocates device memory. Host memory is
+ * workspaces, plan memory). The library never allocates device memory at run time; its one
+ * fixed device array (4 MiB per device, for cloth_reduce_fp64_noalloc) is part of the loaded
+ * code object. Host memory is
  * allocated only for plan handles (pecnn_plan_create / pecnn_plan_destroy) and the
  * rollout's graph cache inside a plan (its graphs, a capture stream and one pinned int).
  *
@@ -234,6 +236,21 @@ int pecnn_rollout(pecnn_plan* plan, const pecnn_model* model, const cloth_ms_par
    out: device double [4n]. ws: pecnn_workspace_bytes(plan, NULL, PECNN_WS_REDUCE). */
 int cloth_reduce_fp64(const pecnn_plan* plan, const cloth_ms_params* p, const float* s,
                       const float* s_ref, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Allocation-free cloth_reduce_fp64, for callers that cannot allocate device memory or hand
+   over a workspace (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc). Same arguments without ws, the same kernels and the same results bit for bit: the
+   per-chunk FP64 partials live in a fixed device array inside the library, 4 MiB per device,
+   held until the process ends. Its device address is looked up once per device (by
+   pecnn_plan_create, or else by the first call with that device current). A plan with more
+   than PECNN_NOALLOC_REDUCE_MAX_CHUNKS node chunks (instance b has ceil(H_b W_b / 256) chunks;
+   e.g. 512 cloths of 256 x 256 are 2^17 chunks) returns PECNN_E_WORKSPACE with no side effect.
+   Every call on one device shares that array: calls that can overlap on one device (other
+   streams, other host threads) race and must be serialised by the caller. Each call writes
+   every partial it reads, so the array never needs clearing. Calls no allocating routine. */
+#define PECNN_NOALLOC_REDUCE_MAX_CHUNKS 131072
+int cloth_reduce_fp64_noalloc(const pecnn_plan* plan, const cloth_ms_params* p, const float* s,
+                              const float* s_ref, double* out, void* stream);
 
 /* ------------------------------------------------------------------ training helpers */
 

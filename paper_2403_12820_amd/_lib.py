@@ -73,6 +73,7 @@ def lib():
         "pecnn_backward": ([vp, P(Model), vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "pecnn_rollout": ([vp, P(Model), P(MsParams), P(Guard), vp, vp, i32, vp, vp, vp, sz, vp], i32),
         "cloth_reduce_fp64": ([vp, P(MsParams), vp, vp, vp, vp, sz, vp], i32),
+        "cloth_reduce_fp64_noalloc": ([vp, P(MsParams), vp, vp, vp, vp], i32),
         "pecnn_loss_mse": ([vp, vp, vp, f32, f32, f32, i64, vp, vp, vp, sz, vp], i32),
         "pecnn_adam_step": ([i64, f32, f32, f32, f32, i32, vp, vp, vp, vp, vp], i32),
         "pecnn_gather_windows": ([vp, i64, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp], i32),
@@ -95,7 +96,8 @@ def exported_symbols():
             "pecnn_plan_set_tiles", "pecnn_plan_get_tiles", "pecnn_plan_set_pressure", "pecnn_plan_set_spheres",
             "cloth_ms_step",
             "pecnn_theta_size", "pecnn_cell_theta_size",
-            "pecnn_forward", "pecnn_backward", "pecnn_rollout", "cloth_reduce_fp64", "pecnn_loss_mse",
+            "pecnn_forward", "pecnn_backward", "pecnn_rollout", "cloth_reduce_fp64", "cloth_reduce_fp64_noalloc",
+            "pecnn_loss_mse",
             "pecnn_adam_step", "pecnn_gather_windows", "pecnn_workspace_bytes", "pecnn_autotune",
             "pecnn_status_string", "pecnn_last_error", "pecnn_version"]
 
@@ -254,6 +256,11 @@ def cloth_reduce_fp64(plan: Plan, params: MsParams, s, s_ref, out, ws=None, stre
         ws = plan.workspace(WS_REDUCE)
     check(lib().cloth_reduce_fp64(plan.handle, C.byref(params), _ptr(s), _ptr(s_ref), _ptr(out), _ptr(ws), ws.numel(),
                                   _stream(stream)), "cloth_reduce_fp64")
+
+
+def cloth_reduce_fp64_noalloc(plan: Plan, params: MsParams, s, s_ref, out, stream=None):
+    check(lib().cloth_reduce_fp64_noalloc(plan.handle, C.byref(params), _ptr(s), _ptr(s_ref), _ptr(out),
+                                          _stream(stream)), "cloth_reduce_fp64_noalloc")
 
 
 def pecnn_loss_mse(plan: Plan, s_hat, s_true, sx, sv, w, n_free, loss, g_hat, ws=None, stream=None):

@@ -30,6 +30,7 @@ int sphere_adjoint_launch(const pecnn_plan*, float, const float*, const float*, 
 int zero_floats_launch(float*, int64_t, hipStream_t);
 size_t reduce_ws_bytes(const pecnn_plan*);
 int reduce_launch(const pecnn_plan*, const MsParamsDev&, const float*, const float*, double*, void*, hipStream_t);
+int reduce_scratch(double**);
 int loss_launch(const pecnn_plan*, const float*, const float*, float, float, float, int64_t, double*, float*, void*,
                 hipStream_t);
 int adam_launch(int64_t, float, float, float, float, int, float*, float*, float*, const float*, hipStream_t);
@@ -416,6 +417,9 @@ int pecnn_plan_create(const pecnn_batch_desc* d, const uint8_t* pin, void* dev_m
   for (int b = 0; b < n; ++b)
     if (p->W[b] % 4 != 0 || p->off[b] % 4 != 0) p->vec4 = 0;
   p->graph_cache = nullptr;
+  // set-up of the allocation-free diagnostics on this device; a failure here is reported by
+  // cloth_reduce_fp64_noalloc, which looks the address up again
+  if (reduce_scratch(nullptr) != PECNN_OK) set_error("");
   *out = p;
   return PECNN_OK;
 }
@@ -610,6 +614,23 @@ int cloth_reduce_fp64(const pecnn_plan* p, const cloth_ms_params* prm, const flo
   if (!s || !out) { set_error("null state or output"); return PECNN_E_INVALID; }
   if (!ws || ws_bytes < reduce_ws_bytes(p)) { set_error("reduce workspace too small"); return PECNN_E_WORKSPACE; }
   return reduce_launch(p, ms_params_dev(prm), s, s_ref, out, ws, (hipStream_t)stream);
+}
+
+int cloth_reduce_fp64_noalloc(const pecnn_plan* p, const cloth_ms_params* prm, const float* s, const float* s_ref,
+                              double* out, void* stream) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((rc = check_ms_params(prm))) return rc;
+  if (!s || !out) { set_error("null state or output"); return PECNN_E_INVALID; }
+  const int chunks = p->n_tiles[kCfgChunk];
+  if (chunks > PECNN_NOALLOC_REDUCE_MAX_CHUNKS) {
+    set_error("the plan has %d node chunks; the allocation-free reduction holds partials for at most %d", chunks,
+              PECNN_NOALLOC_REDUCE_MAX_CHUNKS);
+    return PECNN_E_WORKSPACE;
+  }
+  double* part = nullptr;
+  if ((rc = reduce_scratch(&part))) return rc;
+  return reduce_launch(p, ms_params_dev(prm), s, s_ref, out, part, (hipStream_t)stream);
 }
 
 int pecnn_loss_mse(const pecnn_plan* p, const float* s_hat, const float* s_true, float sx, float sv, float w,

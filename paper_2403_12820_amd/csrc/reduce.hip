@@ -2,6 +2,8 @@
 // Adam (Table 1) and the training-window gather. Reductions are two-stage with a fixed order
 // (per-chunk sums across lanes and waves, then per-instance or global sums in index order):
 // bitwise reproducible run to run.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace pecnn {
@@ -159,6 +161,40 @@ int reduce_launch(const pecnn_plan* plan, const MsParamsDev& P, const float* s, 
   hipLaunchKernelGGL(reduce_final_kernel, dim3(plan->n), dim3(256), 0, st, plan->d_prefix[kCfgChunk],
                      plan->n, partial, out);
   PECNN_LAUNCH_CHECK("reduce_final_kernel");
+  return PECNN_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free diagnostics
+// The per-chunk partials of cloth_reduce_fp64_noalloc live in this file-scope array: each device
+// holds its own copy, at its own address, until the process ends. In host code the array's name
+// is only a stand-in, so kernels get the address looked up below (once per device, with that
+// device current), never the name.
+static_assert(PECNN_NOALLOC_REDUCE_MAX_CHUNKS % 64 == 0, "partials array size");
+static __device__ __align__(256) double scratch[4 * PECNN_NOALLOC_REDUCE_MAX_CHUNKS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices];
+}  // namespace
+
+int reduce_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d is beyond the %d devices the library tracks", dev, kMaxDevices);
+    return PECNN_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) { set_error("hipGetSymbolAddress(scratch) gave a null address"); return PECNN_E_HIP; }
+    g_scratch[dev] = (double*)ptr;
+  }
+  if (out) *out = g_scratch[dev];
   return PECNN_OK;
 }
 
