@@ -124,6 +124,7 @@ class Trainer:
         self.t = 0
         self.model = L.make_model(self.theta, ch, L.PECNN_FP32, dt=dt_nn, cell=cell_code(cell))
         self.device = device
+        self._torch = torch
 
     def _buffers(self, plan, U, N, phys=False):
         import torch
@@ -175,6 +176,33 @@ class Trainer:
             g_prev = grads[t - 2] if t >= 2 else None
             L.pecnn_backward(plan, self.model, S[t], S[t + 1], grads[t], g_cur, g_prev, self.g, ws=self.ws_b)
         return self.loss
+
+    def save(self, path, **extra):
+        """Checkpoint: theta, the Adam moments and step count, plus the caller's extra fields
+        (arrays or JSON-able values), in one .npz file that loads without pickle."""
+        arrays = {"theta": self.theta.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
+                  "t": np.int64(self.t), "ch": np.int64(self.ch), "cell": np.array(self.cell)}
+        for k, v in extra.items():
+            arrays[k] = v if isinstance(v, np.ndarray) else np.array(json.dumps(v))
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, **arrays)
+        os.replace(tmp, path)
+
+    def restore(self, path):
+        """Load a checkpoint written by save(); returns its extra fields (JSON ones decoded)."""
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["ch"]) != self.ch or str(z["cell"]) != self.cell:
+                raise ValueError("checkpoint of another cell")
+            for name in ("theta", "m", "v"):
+                getattr(self, name).copy_(self._torch.from_numpy(z[name]))
+            self.t = int(z["t"])
+            extra = {}
+            for k in z.files:
+                if k in ("theta", "m", "v", "t", "ch", "cell"):
+                    continue
+                a = z[k]
+                extra[k] = json.loads(str(a)) if a.dtype.kind == "U" else a.copy()
+        return extra
 
     def step(self, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0, lr=None, alpha=0.0, sim=None,
              stride=10):
@@ -247,15 +275,22 @@ def rollout_rms(traj: Trajectories, scene_ids, theta, ch, n_frames, precision=0,
 
 
 class SizeClass:
-    """Trajectories of one grid size with their loss scales, training and held-out windows."""
+    """Trajectories of one grid size with their loss scales, training and held-out windows.
+    Of the n_scenes scenes the last n_test are test scenes, the n_val before them selection
+    scenes: the kept theta is chosen on the selection scenes, and the test scenes are used only
+    to report the result (never for training or selection)."""
 
-    def __init__(self, size, n_scenes, n_val, seed, mat, n_frames, stride, n_win, n_unroll, device):
+    def __init__(self, size, n_scenes, n_val, seed, mat, n_frames, stride, n_win, n_unroll, device, n_test=0):
         self.size = size
         scenes = I.random_scenes([(size, size)] * n_scenes, seed=seed)
         self.traj = Trajectories(scenes, mat, n_frames, stride, device)
         self.sx, self.sv = self.traj.increment_scales()
-        self.train_ids = list(range(n_scenes - n_val))
-        self.val_ids = list(range(n_scenes - n_val, n_scenes))
+        n_fit = n_scenes - n_val - n_test
+        if n_fit < 1 or n_val < 1 or n_test < 0:
+            raise ValueError("need at least one training and one selection scene")
+        self.train_ids = list(range(n_fit))
+        self.val_ids = list(range(n_fit, n_fit + n_val))
+        self.test_ids = list(range(n_fit + n_val, n_scenes))
         self.wb = WindowBatch(self.traj, self.train_ids, n_win, n_unroll, device)
         # fixed held-out windows for a deterministic validation loss
         self.wv = WindowBatch(self.traj, self.val_ids, n_win, n_unroll, device)
@@ -264,26 +299,35 @@ class SizeClass:
 
 def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=32, lr=1e-3, seed=4,
           n_frames=201, stride=10, log_every=500, eval_frames=100, device="cuda", verbose=True, lr_final=None,
-          alpha=0.0, cell="conv", sizes=None):
+          alpha=0.0, cell="conv", sizes=None, n_test=0, checkpoint=None, checkpoint_every=0, resume=None,
+          stop_after=None):
     """Adam at lr, annealed along a cosine to lr_final over the run when lr_final is given (the
     post-process cosine schedule of Table 1); alpha weighs the physics term of eq. (8).
     sizes: grid sides trained together, n_scenes each (the first with `seed`, the others with
     their own seeds); iterations take their minibatches from the sizes in turn, each size with
-    its own increment scales, and the kept theta has the lowest mean held-out error over them."""
+    its own increment scales, and the kept theta has the lowest mean held-out error over them.
+    n_val selection scenes choose the kept theta; n_test further scenes, which neither training
+    nor selection sees, give the reported gain (trained against untrained).
+    checkpoint / checkpoint_every: write theta, the Adam state, the iteration, the sampler's RNG
+    state and the best theta so far every that many iterations; resume: continue from such a file
+    (the run then matches an uninterrupted one bit for bit); stop_after: end the loop after that
+    iteration (with its checkpoint) and return (None, None)."""
     import torch
     mat = I.Material()
     t0 = time.time()
     sizes = [size] if not sizes else list(sizes)
-    classes = [SizeClass(sz, n_scenes, n_val, seed + 1000 * k, mat, n_frames, stride, n_win, n_unroll, device)
-               for k, sz in enumerate(sizes)]
+    if n_frames <= eval_frames:
+        raise ValueError("the trajectories (%d frames) must reach the evaluation frame %d" % (n_frames, eval_frames))
+    classes = [SizeClass(sz, n_scenes, n_val, seed + 1000 * k, mat, n_frames, stride, n_win, n_unroll, device,
+                         n_test) for k, sz in enumerate(sizes)]
     t_gen = time.time() - t0
     tr = Trainer(ch=ch, dt_nn=stride * mat.dt, lr=lr, device=device, cell=cell)
     ch = tr.ch
     theta0 = tr.theta.cpu().numpy().copy()
     rng = np.random.default_rng(seed)
 
-    def val_rms(theta):
-        return [rollout_rms(c.traj, c.val_ids, theta, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
+    def val_rms(theta, which="val_ids"):
+        return [rollout_rms(c.traj, getattr(c, which), theta, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
                             cell=cell)[0] for c in classes]
 
     def val_loss():
@@ -293,7 +337,16 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     curve = []
     t1 = time.time()
     best = (math.inf, theta0)
-    for it in range(1, iters + 1):
+    it_start = 1
+    if resume is not None:
+        ex = tr.restore(resume)
+        if ex["iters"] != iters:
+            raise ValueError("the checkpoint belongs to a run of %d iterations" % ex["iters"])
+        it_start = int(ex["iteration"]) + 1
+        rng.bit_generator.state = ex["rng"]
+        curve = [tuple(c) for c in ex["curve"]]
+        best = (float(ex["best_rms"]), ex["best_theta"])
+    for it in range(it_start, iters + 1):
         c = classes[(it - 1) % len(classes)]
         plan, n_free = c.wb.sample(rng)
         lr_t = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (it - 1) / iters))
@@ -311,11 +364,24 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
                 print("iter %6d loss %.5g  val loss %.5g  val rms@%d %.4g  (%.1f s)" % (
                     it, lv, vl, eval_frames, rms_v, time.time() - t1), flush=True)
         plan.close()
+        if checkpoint and checkpoint_every > 0 and (it % checkpoint_every == 0 or it == iters):
+            tr.save(checkpoint, iteration=it, iters=iters, rng=rng.bit_generator.state, curve=curve,
+                    best_rms=best[0], best_theta=np.asarray(best[1], np.float32))
+        if stop_after is not None and it >= stop_after:
+            return None, None
     torch.cuda.synchronize()
     t_train = time.time() - t1
     theta_best = best[1]
     rms_trained = val_rms(theta_best)
     rms_untrained = val_rms(theta0)
+    test = {}
+    if n_test > 0:
+        t_tr, t_un = val_rms(theta_best, "test_ids"), val_rms(theta0, "test_ids")
+        test = {"test_scenes": n_test,
+                "test_rms_trained": np.concatenate(t_tr).tolist(),
+                "test_rms_untrained": np.concatenate(t_un).tolist(),
+                "test_rms_trained_mean": float(np.mean([r.mean() for r in t_tr])),
+                "test_rms_untrained_mean": float(np.mean([r.mean() for r in t_un]))}
     val_loss_final = val_loss()
     tr.theta.copy_(torch.tensor(theta_best, device=device))
     val_loss_best = val_loss()
@@ -330,7 +396,7 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
         "val_rms_trained_mean": float(np.mean([r.mean() for r in rms_trained])),
         "val_rms_untrained_mean": float(np.mean([r.mean() for r in rms_untrained])),
         "eval_frames": eval_frames, "val_loss_first": curve[0][2], "val_loss_best_theta": val_loss_best,
-        "val_loss_final_theta": val_loss_final,
+        "val_loss_final_theta": val_loss_final, **test,
     }
     if len(classes) > 1:
         report["val_rms_trained_by_size"] = {str(c.size): float(r.mean()) for c, r in zip(classes, rms_trained)}
@@ -340,10 +406,14 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--scenes", type=int, default=64)
+    ap.add_argument("--scenes", type=int, default=72, help="trajectories per grid size: training, then selection, then test scenes")
     ap.add_argument("--size", type=int, default=64)
     ap.add_argument("--sizes", default=None, help="comma-separated grid sides trained together (overrides --size)")
-    ap.add_argument("--val", type=int, default=8)
+    ap.add_argument("--val", type=int, default=8, help="selection scenes (choose the kept theta)")
+    ap.add_argument("--test", type=int, default=8, help="test scenes (reported only)")
+    ap.add_argument("--stride", type=int, default=10, help="simulator steps per network frame")
+    ap.add_argument("--sim-steps", type=int, default=2000, help="simulator steps per training trajectory")
+    ap.add_argument("--eval-frames", type=int, default=100, help="network frames of the held-out rollouts")
     ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--minibatch", type=int, default=32)
     ap.add_argument("--unroll", type=int, default=8)
@@ -356,10 +426,19 @@ def main():
     ap.add_argument("--log-every", type=int, default=500)
     ap.add_argument("--out", default=os.path.join(HERE, "weights", "pecnn_ch32.npy"))
     ap.add_argument("--report", default=None)
+    ap.add_argument("--checkpoint", default=None, help="checkpoint file (.npz), written every --checkpoint-every")
+    ap.add_argument("--checkpoint-every", type=int, default=1000)
+    ap.add_argument("--resume", default=None, help="continue from this checkpoint")
     args = ap.parse_args()
+    if args.sim_steps % args.stride:
+        raise SystemExit("--sim-steps must be a multiple of --stride")
     theta, report = train(args.scenes, args.size, args.val, args.iters, args.minibatch, args.unroll, args.ch,
-                          args.lr, args.seed, log_every=args.log_every, lr_final=args.lr_final, alpha=args.alpha,
-                          cell=args.cell, sizes=[int(x) for x in args.sizes.split(",")] if args.sizes else None)
+                          args.lr, args.seed, n_frames=args.sim_steps // args.stride + 1, stride=args.stride,
+                          log_every=args.log_every, eval_frames=args.eval_frames, lr_final=args.lr_final,
+                          alpha=args.alpha, cell=args.cell,
+                          sizes=[int(x) for x in args.sizes.split(",")] if args.sizes else None, n_test=args.test,
+                          checkpoint=args.checkpoint, checkpoint_every=args.checkpoint_every if args.checkpoint else 0,
+                          resume=args.resume)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, theta.astype(np.float32), allow_pickle=False)
     rep = args.report or os.path.splitext(args.out)[0] + "_report.json"

@@ -158,13 +158,60 @@ def test_trainer_rejects_bad_alpha(L):
 
 
 def test_training_reduces_loss_and_beats_untrained(L):
-    """A short training run on small synthetic trajectories lowers the loss and the 20-frame
-    rollout error of held-out scenes compared with the untrained network."""
+    """A short training run on small synthetic trajectories: the held-out loss of the final
+    parameters is below that of the initial ones, and on test scenes that neither training nor
+    the choice of the kept parameters saw, the kept network's 20-frame rollout error is below 0.97
+    of the untrained network's (600 iterations at 24 x 24 learn little more than gravity; the
+    committed weights are held to a larger gain below)."""
     from paper_2403_12820_amd.train import train
-    theta, rep = train(n_scenes=12, size=24, n_val=3, iters=600, n_win=8, n_unroll=4, ch=16, lr=1e-3,
+    theta, rep = train(n_scenes=15, size=24, n_val=3, n_test=3, iters=600, n_win=8, n_unroll=4, ch=16, lr=1e-3,
                        seed=3, n_frames=41, stride=10, log_every=200, eval_frames=20, verbose=False, lr_final=1e-4)
-    # held-out windows: the loss of the final parameters is below the initial one, and the kept
-    # parameters' rollout error on held-out scenes is below the untrained network's
+    print("test-scene rms: trained %.4g untrained %.4g; selection scenes: %.4g %.4g" % (
+        rep["test_rms_trained_mean"], rep["test_rms_untrained_mean"], rep["val_rms_trained_mean"],
+        rep["val_rms_untrained_mean"]))
     assert rep["val_loss_final_theta"] < rep["val_loss_first"], rep["loss_curve"]
-    assert rep["val_rms_trained_mean"] < rep["val_rms_untrained_mean"], rep
+    assert rep["test_rms_trained_mean"] < 0.97 * rep["test_rms_untrained_mean"], rep
     assert np.all(np.isfinite(theta))
+
+
+def test_checkpoint_resume_matches_straight_run(L, tmp_path):
+    """Training stopped at a checkpoint and resumed from it (theta, Adam moments and step, the
+    sampler's RNG state, the best parameters so far) ends bit for bit where an uninterrupted run
+    ends."""
+    from paper_2403_12820_amd.train import train
+    kw = dict(n_scenes=6, size=16, n_val=1, n_test=1, iters=30, n_win=4, n_unroll=3, ch=16, lr=1e-3, seed=5,
+              n_frames=21, stride=10, log_every=10, eval_frames=10, verbose=False, lr_final=1e-4)
+    a, b = str(tmp_path / "straight.npz"), str(tmp_path / "resumed.npz")
+    th_a, _ = train(**kw, checkpoint=a, checkpoint_every=15)
+    assert train(**kw, checkpoint=b, checkpoint_every=15, stop_after=15) == (None, None)
+    with np.load(b, allow_pickle=False) as z:
+        assert int(z["t"]) == 15
+    th_b, _ = train(**kw, checkpoint=b, checkpoint_every=15, resume=b)
+    np.testing.assert_array_equal(th_a, th_b)
+    with np.load(a, allow_pickle=False) as za, np.load(b, allow_pickle=False) as zb:
+        assert int(za["t"]) == int(zb["t"]) == 30
+        for k in ("theta", "m", "v", "best_theta"):
+            np.testing.assert_array_equal(za[k], zb[k])
+        assert str(za["rng"]) == str(zb["rng"])
+
+
+def test_committed_weights_gain_on_unseen_scenes(L):
+    """The committed Ch = 32 weights against the untrained initial weights on the eight 64 x 64
+    test scenes of the training draw (scenes 64..71 of seed 4: the committed run trained on
+    scenes 0..55 and chose its kept parameters on 56..63), 100 frames of 10 simulator steps: the
+    trained network's mean position RMS is at most 0.6 of the untrained one's (measured: 0.165
+    against 0.520). Scene by scene it is lower on seven of the eight; on one cloth pinned at its four
+    corners it is higher (0.43 against 0.25), so no per-scene bound is asserted."""
+    import os
+    from paper_2403_12820_amd.train import Trajectories, rollout_rms
+    w = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_12820_amd", "weights",
+                     "pecnn_ch32.npy")
+    theta = np.load(w, allow_pickle=False).astype(np.float32)
+    scenes = I.random_scenes([(64, 64)] * 72, seed=4)[64:]
+    traj = Trajectories(scenes, MAT, 101, 10)
+    ids = list(range(len(scenes)))
+    rms_t, _ = rollout_rms(traj, ids, theta, 32, 100)
+    rms_u, _ = rollout_rms(traj, ids, I.init_theta(32, seed=1), 32, 100)
+    print("unseen 64x64 scenes, 100 frames: trained %s, untrained %s" % (np.round(rms_t, 4), np.round(rms_u, 4)))
+    assert rms_t.mean() <= 0.6 * rms_u.mean(), (rms_t, rms_u)
+    assert np.all(np.isfinite(rms_t)), rms_t
