@@ -8,11 +8,18 @@ mass-spring step on the same batch, timed beside it over the same simulated time
 The position RMS of the rollout against that simulator run (FP64 reduction, divided by the
 cloth width) is reported with it. Inputs are synthetic and resident in HBM before timing.
 
+The stride (simulator steps per frame) is 4 by default: with the committed stride-4 weights the
+rollout stays within 1e-2 of the cloth width after 100 frames; the stride-10 weights
+(--stride 10) do not (about 4e-2), so their higher simulator-equivalent rate is not a rate at
+that error.
+
 Printed (one JSON line): the contract fields, plus
-  roofline      - the dominant kernel (the CNN frame) timed alone with HIP events on its stream:
-                  algorithmic bytes per launch / mean launch time, against 8 TB/s HBM;
-                  traffic (measured HBM bytes per launch) from the committed rocprofv3 counter
-                  summary when it was taken on the current kernel source, else null;
+  roofline      - the dominant kernel (the CNN frame) timed alone with HIP events on its stream,
+                  against the ALU roofline that binds it: the method's elementwise FP32 VALU
+                  work per node (alu_ops_per_node) over the lane-operation peak, with the HBM
+                  view (algorithmic bytes per launch against 8 TB/s) beside it; traffic
+                  (measured HBM bytes per launch) from the committed rocprofv3 counter summary
+                  when it was taken on the current kernel source, else null;
   cpu_baseline  - the FP64 oracle's CNN frame on a bounded sample, single thread;
   config        - the workload, raw frame rate, mass-spring rate, RMS and fallbacks, and an
                   untimed accuracy leg: RMS after --acc-frames network frames (default 100, the
@@ -45,8 +52,25 @@ HBM_PEAK_GBS = 8000.0
 CNN_BYTES_PER_NODE = 73  # read S^k and S^{k-1} (24 B each), write S^{k+1} (24 B), pin flag (1 B)
 PAIR_BYTES_PER_NODE = 49  # the pair cell reads S^k only: 24 B + pin flag, writes 24 B
 MS_BYTES_PER_NODE = 49   # read S (24 B), write S' (24 B), pin flag (1 B)
+# The bf16 frame's elementwise arithmetic per node, in FP32 VALU lane operations that the method
+# needs with bf16 operands on the matrix cores (a transcendental counts 4: it issues at a quarter
+# of the full rate, which replacing the frame's rsqrt by a multiply confirms on the device):
+#   position differences of the conv input, 3 channels x 8 taps x 2 fields, and S^k - S^{k-1}: 54
+#   round-to-nearest-even casts of the matrix operands, two per instruction: the conv taps
+#     (2 x 51), phi, n and d (Ch + 2 Ch): (102 + 3 Ch) / 2
+#   eq. (7)'s elementwise part per channel: z = a b, 1 + z^2, n = z r, 1 + phi^2, g = phi r, d = xi g
+#     (6) and two rsqrt (2 x 4)
+#   eq. (5): v' = v + dv + (b_L + dt a_ext), x' = x + dt v': 9
+def alu_ops_per_node(ch):
+    return 54 + (102 + 3 * ch) // 2 + 6 * ch + 8 * ch + 9
+
+
+# FP32 VALU peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, lane operations/s
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cnn_fwd_bf16_128x256x256_traffic.txt")
-WEIGHTS = os.path.join(ROOT, "paper_2403_12820_amd", "weights", "pecnn_ch32.npy")
+WEIGHT_DIR = os.path.join(ROOT, "paper_2403_12820_amd", "weights")
+# trained Ch = 32 weights per stride (simulator steps per network frame)
+WEIGHTS = {4: os.path.join(WEIGHT_DIR, "pecnn_ch32_s4.npy"), 10: os.path.join(WEIGHT_DIR, "pecnn_ch32.npy")}
 PAIR_WEIGHTS = os.path.join(ROOT, "paper_2403_12820_amd", "weights", "pecnn_pair.npy")
 CNN_TILES = {0: "64, 4", 1: "32, 8", 2: "16, 16", 3: "64, 8"}
 
@@ -62,7 +86,7 @@ def measured_traffic(nodes):
     return float(tr["bytes_per_launch"])
 
 
-def load_theta(ch, cell="conv", path=None):
+def load_theta(ch, cell="conv", path=None, stride=4):
     from paper_2403_12820_amd import inputs as I
     if path is not None:  # weights named on the command line: used as they are, or refused
         th = np.load(path, allow_pickle=False).astype(np.float32)
@@ -76,16 +100,17 @@ def load_theta(ch, cell="conv", path=None):
             if th.size == I.PAIR_THETA_SIZE:
                 return th, "trained"
         return I.init_pair_theta(seed=1), "initial (s = 1/L, weights N(0, 0.02) seed 1)"
-    if ch == 32 and os.path.exists(WEIGHTS):
-        th = np.load(WEIGHTS, allow_pickle=False).astype(np.float32)
+    w = WEIGHTS.get(stride)
+    if ch == 32 and w is not None and os.path.exists(w):
+        th = np.load(w, allow_pickle=False).astype(np.float32)
         if th.size == I.theta_size(ch):
-            return th, "trained"
+            return th, "trained (%s)" % os.path.basename(w)
     return I.init_theta(ch, seed=1), "random N(0, 0.02) seed 1"
 
 
 def _oracle_frames(args):
     """One worker: FP64 oracle frames of one 256 x 256 cloth (seeded per worker) for budget_s."""
-    ch, theta, budget_s, cell, seed = args
+    ch, theta, budget_s, cell, seed, dt = args
     import oracle
     from paper_2403_12820_amd import inputs as I
     sc = I.random_scenes([(256, 256)], seed=seed)[0]
@@ -96,9 +121,9 @@ def _oracle_frames(args):
     sp, sk = s, s
     while True:
         if cell == "pair":
-            sn, _ = oracle.pair_forward(256, 256, 1.0, 5e-3, sc.a_ext, sc.pin, th, sk)
+            sn, _ = oracle.pair_forward(256, 256, 1.0, dt, sc.a_ext, sc.pin, th, sk)
         else:
-            sn, _ = oracle.cnn_forward(256, 256, ch, 1.0, 5e-3, sc.a_ext, sc.pin, th, sp, sk)
+            sn, _ = oracle.cnn_forward(256, 256, ch, 1.0, dt, sc.a_ext, sc.pin, th, sp, sk)
         sp, sk = sk, sn
         frames += 1
         if time.perf_counter() - t0 >= budget_s:
@@ -106,11 +131,11 @@ def _oracle_frames(args):
     return frames, time.perf_counter() - t0
 
 
-def cpu_baseline(ch, theta, budget_s=10.0, cell="conv", cores=1, stride=10):
+def cpu_baseline(ch, theta, budget_s=10.0, cell="conv", cores=1, stride=4):
     """The FP64 oracle's frame on 256 x 256 cloths for about budget_s seconds, on `cores` worker
     processes (one cloth each), counted like `value`: nodes x frames x stride / time. Runs before
     the GPU is touched, so the workers are plain forks."""
-    work = [(ch, theta, budget_s, cell, 5 + k) for k in range(cores)]
+    work = [(ch, theta, budget_s, cell, 5 + k, stride * 5e-4) for k in range(cores)]
     if cores == 1:
         res = [_oracle_frames(work[0])]
     else:
@@ -241,6 +266,8 @@ def main():
     ap.add_argument("--instances", type=int, default=128)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--ch", type=int, default=32)
+    ap.add_argument("--stride", type=int, default=4,
+                    help="simulator steps per network frame (the committed weights: 4, and 10)")
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--stretch-max", type=float, default=2.0)
     ap.add_argument("--energy-gain-max", type=float, default=0.2)
@@ -276,9 +303,10 @@ def main():
 
     pair = args.cell == "pair"
     ch = 12 if pair else args.ch
-    theta_np, theta_kind = load_theta(ch, args.cell, args.weights)
+    theta_np, theta_kind = load_theta(ch, args.cell, args.weights, args.stride)
     # the CPU baseline first, before anything touches the GPU
-    cpu = None if args.no_cpu else cpu_baseline(ch, theta_np, args.cpu_seconds, args.cell, args.cpu_cores)
+    cpu = None if args.no_cpu else cpu_baseline(ch, theta_np, args.cpu_seconds, args.cell, args.cpu_cores,
+                                                args.stride)
 
     import torch
     from paper_2403_12820_amd import _lib as L
@@ -287,7 +315,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     mat = I.Material()
-    stride = 10
+    stride = args.stride
     dt_nn = stride * mat.dt
     if args.workload == "uniform":
         sizes = [(args.size, args.size)] * args.instances
@@ -386,6 +414,13 @@ def main():
     rms_acc = rms_of(b, y)
     fb_acc_host = fb_acc.cpu().numpy() != 0
     st_acc = stats_acc.cpu().numpy().reshape(-1, 4)
+    # the same, per pin set of the scenes (the guard's decisions depend on how a cloth hangs)
+    by_pins = {}
+    kinds = np.array([sc.pin_kind for sc in scenes])
+    for kind in sorted(set(kinds.tolist())):
+        sel = kinds == kind
+        by_pins[kind] = {"instances": int(sel.sum()), "fallback_instances": int(fb_acc_host[sel].sum()),
+                         "rms_width_mean": float(rms_acc[sel].mean()), "rms_width_max": float(rms_acc[sel].max())}
 
     # ---- dominant kernel alone, HIP events on the launch stream
     st = torch.cuda.current_stream()
@@ -410,6 +445,25 @@ def main():
     achieved = alg_bytes / t_kernel / 1e9
 
     traffic = measured_traffic(N) if args.workload == "uniform" and not pair else None
+
+    kname = ("ms_step_kernel (pair-cell frame, cfg %d)" % ms_cfg if pair else
+             "cnn_fwd_bf16_kernel<32, %s>" % CNN_TILES.get(cnn_cfg, "?"))
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
+           "algorithmic_bytes_per_launch": alg_bytes}
+    if pair:
+        roof = hbm
+    else:
+        # the frame's elementwise arithmetic takes longer than its HBM traffic at the peaks
+        # (alu_ops_per_node / 16 lanes per SIMD cycle against 73 B / 8 TB/s), so the ALU roofline binds
+        ops = alu_ops_per_node(ch) * N
+        a_tops = ops / t_kernel / 1e12
+        roof = {"bound": "alu", "achieved": a_tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": a_tops / ALU_PEAK_TOPS, "traffic": traffic, "kernel": kname,
+                "algorithmic_ops_per_launch": ops, "ops_per_node": alu_ops_per_node(ch),
+                "floor_ms": 1e3 * ops / (ALU_PEAK_TOPS * 1e12),
+                "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac", "algorithmic_bytes_per_launch")},
+                "hbm_floor_ms": 1e3 * alg_bytes / (HBM_PEAK_GBS * 1e9)}
 
     raw = N * args.steps / t_roll
     value = raw * stride
@@ -441,6 +495,7 @@ def main():
                                                            for k in np.nonzero(fb_acc_host)[0])) / N,
             "first_fallback_frame_at_horizon": (int(st_acc[fb_acc_host, 3].min()) if fb_acc_host.any() else None),
             "guarded_rate_over_horizon_node_steps_per_s": N * H_acc * stride / t_acc,
+            "at_horizon_by_pin_set": by_pins,
             "guard": {"stretch_max": args.stretch_max, "energy_gain_max": args.energy_gain_max,
                       "check_every": args.check_every, "frame_err_max": args.frame_err_max},
             "fallback_instances": fell, "fallback_rate": fell / batch.n,
@@ -448,11 +503,7 @@ def main():
             "ms_kernel_gbs": MS_BYTES_PER_NODE * N / t_ms_kernel / 1e9,
             "cnn_kernel_ms": t_kernel * 1e3, "ms_kernel_ms": t_ms_kernel * 1e3,
         },
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("ms_step_kernel (pair-cell frame, cfg %d)" % ms_cfg if pair else
-                                "cnn_fwd_bf16_kernel<32, %s>" % CNN_TILES.get(cnn_cfg, "?")),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+        "roofline": roof,
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libpecnn.so")
+# the in-tree build; PECNN_LIB names another build of the same sources (the sanitizer test's)
+LIB_PATH = os.environ.get("PECNN_LIB") or os.path.join(_HERE, "lib", "libpecnn.so")
 
 PECNN_FP32, PECNN_BF16 = 0, 1
 CELL_CONV, CELL_PAIR = 0, 1
