@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--frame-err-max", type=float, default=0.0,
                     help="bound of the guard's frame-error test (RMS / width of one frame against the "
                          "simulator); 0 = off")
+    ap.add_argument("--simulate-below", type=int, default=0,
+                    help="cloths whose shorter side is below this run on the simulator from the start")
     ap.add_argument("--acc-frames", type=int, default=100,
                     help="network frames of the untimed accuracy leg (the RMS target's horizon)")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -345,6 +347,9 @@ def main():
     guard.check_every, guard.substeps = args.check_every, stride
     guard.frame_err_max = args.frame_err_max
     fb = torch.zeros(batch.n, dtype=torch.int32, device=dev)
+    # size-aware guard: cloths narrower than --simulate-below start on the simulator (the caller
+    # may preset fall-back flags): the network's error relative to the width grows as cloths shrink
+    fb0 = torch.tensor((np.minimum(batch.H, batch.W) < args.simulate_below).astype(np.int32), device=dev)
     stats = torch.zeros(4 * batch.n, dtype=torch.float64, device=dev)
     ws = plan.workspace(L.WS_ROLLOUT)
 
@@ -354,12 +359,12 @@ def main():
     for frames in (args.warmup, args.steps):
         a.copy_(s0)
         b.copy_(s0)
-        fb.zero_()
+        fb.copy_(fb0)
         L.pecnn_rollout(plan, model, sim, guard, a, b, frames, fb, stats, ws)
         torch.cuda.synchronize()
     a.copy_(s0)
     b.copy_(s0)
-    fb.zero_()
+    fb.copy_(fb0)
     torch.cuda.synchronize()
 
     # ---- timed region: K network frames of the batch
@@ -403,7 +408,7 @@ def main():
     for rep in range(2):
         a.copy_(s0)
         b.copy_(s0)
-        fb_acc.zero_()
+        fb_acc.copy_(fb0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         L.pecnn_rollout(plan, model, sim, guard, a, b, H_acc, fb_acc, stats_acc, ws)
@@ -497,7 +502,8 @@ def main():
             "guarded_rate_over_horizon_node_steps_per_s": N * H_acc * stride / t_acc,
             "at_horizon_by_pin_set": by_pins,
             "guard": {"stretch_max": args.stretch_max, "energy_gain_max": args.energy_gain_max,
-                      "check_every": args.check_every, "frame_err_max": args.frame_err_max},
+                      "check_every": args.check_every, "frame_err_max": args.frame_err_max,
+                      "simulate_below": args.simulate_below, "preset_instances": int(fb0.sum())},
             "fallback_instances": fell, "fallback_rate": fell / batch.n,
             "fallback_node_fraction": float(sum(int(batch.H[b]) * int(batch.W[b]) for b in np.nonzero(fb_host)[0])) / N,
             "ms_kernel_gbs": MS_BYTES_PER_NODE * N / t_ms_kernel / 1e9,

@@ -300,7 +300,7 @@ class SizeClass:
 def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=32, lr=1e-3, seed=4,
           n_frames=201, stride=10, log_every=500, eval_frames=100, device="cuda", verbose=True, lr_final=None,
           alpha=0.0, cell="conv", sizes=None, n_test=0, checkpoint=None, checkpoint_every=0, resume=None,
-          stop_after=None):
+          stop_after=None, select_size=None, select_seed=6, n_select=8):
     """Adam at lr, annealed along a cosine to lr_final over the run when lr_final is given (the
     post-process cosine schedule of Table 1); alpha weighs the physics term of eq. (8).
     sizes: grid sides trained together, n_scenes each (the first with `seed`, the others with
@@ -311,7 +311,10 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     checkpoint / checkpoint_every: write theta, the Adam state, the iteration, the sampler's RNG
     state and the best theta so far every that many iterations; resume: continue from such a file
     (the run then matches an uninterrupted one bit for bit); stop_after: end the loop after that
-    iteration (with its checkpoint) and return (None, None)."""
+    iteration (with its checkpoint) and return (None, None).
+    select_size: choose the kept theta instead on n_select scenes of that grid size (their own
+    draw, select_seed), by the largest rollout error at eval_frames among them: the error of a
+    local cell grows with the cloth's size, and a rollout is judged by its worst instance."""
     import torch
     mat = I.Material()
     t0 = time.time()
@@ -329,6 +332,17 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
     def val_rms(theta, which="val_ids"):
         return [rollout_rms(c.traj, getattr(c, which), theta, ch, eval_frames, dt_nn=stride * mat.dt, device=device,
                             cell=cell)[0] for c in classes]
+
+    sel = None
+    if select_size:
+        sel_scenes = I.random_scenes([(select_size, select_size)] * n_select, seed=select_seed)
+        sel = Trajectories(sel_scenes, mat, eval_frames + 1, stride, device)
+
+    def select_metric(theta):
+        if sel is None:
+            return float(np.mean([r.mean() for r in val_rms(theta)]))
+        return float(rollout_rms(sel, list(range(n_select)), theta, ch, eval_frames, dt_nn=stride * mat.dt,
+                                 device=device, cell=cell)[0].max())
 
     def val_loss():
         return float(np.mean([eval_loss(tr, c.wv, c.val_plan, c.val_free, c.sx, c.sv, alpha=alpha, sim=c.traj.sim,
@@ -357,12 +371,13 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
             curve.append((it, lv, vl))
             if not np.isfinite(lv):
                 raise FloatingPointError("training diverged at iteration %d" % it)
-            rms_v = float(np.mean([r.mean() for r in val_rms(tr.theta.cpu().numpy())]))
+            rms_v = select_metric(tr.theta.cpu().numpy())
             if rms_v < best[0]:
                 best = (rms_v, tr.theta.cpu().numpy().copy())
             if verbose:
-                print("iter %6d loss %.5g  val loss %.5g  val rms@%d %.4g  (%.1f s)" % (
-                    it, lv, vl, eval_frames, rms_v, time.time() - t1), flush=True)
+                print("iter %6d loss %.5g  val loss %.5g  %s rms@%d %.4g  (%.1f s)" % (
+                    it, lv, vl, "selection" if sel is None else "max %dx%d" % (select_size, select_size),
+                    eval_frames, rms_v, time.time() - t1), flush=True)
         plan.close()
         if checkpoint and checkpoint_every > 0 and (it % checkpoint_every == 0 or it == iters):
             tr.save(checkpoint, iteration=it, iters=iters, rng=rng.bit_generator.state, curve=curve,
@@ -397,6 +412,10 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
         "val_rms_untrained_mean": float(np.mean([r.mean() for r in rms_untrained])),
         "eval_frames": eval_frames, "val_loss_first": curve[0][2], "val_loss_best_theta": val_loss_best,
         "val_loss_final_theta": val_loss_final, **test,
+        "selection": ({"scenes": "the selection scenes of the training draw", "metric": "mean RMS / width"}
+                      if sel is None else {"size": select_size, "seed": select_seed, "scenes": n_select,
+                                            "metric": "largest RMS / width"}),
+        "selection_best": best[0],
     }
     if len(classes) > 1:
         report["val_rms_trained_by_size"] = {str(c.size): float(r.mean()) for c, r in zip(classes, rms_trained)}
@@ -414,6 +433,10 @@ def main():
     ap.add_argument("--stride", type=int, default=10, help="simulator steps per network frame")
     ap.add_argument("--sim-steps", type=int, default=2000, help="simulator steps per training trajectory")
     ap.add_argument("--eval-frames", type=int, default=100, help="network frames of the held-out rollouts")
+    ap.add_argument("--select-size", type=int, default=None,
+                    help="choose the kept theta on scenes of this grid size (largest error), not the selection scenes")
+    ap.add_argument("--select-seed", type=int, default=6)
+    ap.add_argument("--select-scenes", type=int, default=8)
     ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--minibatch", type=int, default=32)
     ap.add_argument("--unroll", type=int, default=8)
@@ -438,7 +461,8 @@ def main():
                           alpha=args.alpha, cell=args.cell,
                           sizes=[int(x) for x in args.sizes.split(",")] if args.sizes else None, n_test=args.test,
                           checkpoint=args.checkpoint, checkpoint_every=args.checkpoint_every if args.checkpoint else 0,
-                          resume=args.resume)
+                          resume=args.resume, select_size=args.select_size, select_seed=args.select_seed,
+                          n_select=args.select_scenes)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, theta.astype(np.float32), allow_pickle=False)
     rep = args.report or os.path.splitext(args.out)[0] + "_report.json"
