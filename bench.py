@@ -95,7 +95,7 @@ def load_theta(ch, cell="conv", path=None, stride=4):
             raise SystemExit("%s holds %d parameters, the %s cell needs %d" % (path, th.size, cell, need))
         return th, "trained (%s)" % os.path.basename(path)
     if cell == "pair":
-        if os.path.exists(PAIR_WEIGHTS):
+        if stride == 10 and os.path.exists(PAIR_WEIGHTS):  # trained at stride 10
             th = np.load(PAIR_WEIGHTS, allow_pickle=False).astype(np.float32)
             if th.size == I.PAIR_THETA_SIZE:
                 return th, "trained"
