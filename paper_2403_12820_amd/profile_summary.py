@@ -3,6 +3,12 @@
   python -m paper_2403_12820_amd.profile_summary stats KERNEL_STATS.csv OUT.txt --command "..."
       per-kernel calls, average and total duration (from --kernel-trace --stats)
 
+  python -m paper_2403_12820_amd.profile_summary sq --kernel NAME --nodes N --a A.csv --b B.csv \
+      --command-a "..." --command-b "..." OUT.txt
+      SQ and GRBM counters of one kernel (two --pmc passes), mean per dispatch, with derived
+      rates: VALU lane-op slots per node, MFMA per 16 nodes, VALU and MFMA busy fractions and
+      where the waves spend their time.
+
   python -m paper_2403_12820_amd.profile_summary traffic --kernel NAME --nodes N \
       --fetch FETCH.csv --write WRITE.csv --copy-fetch CF.csv --copy-write CW.csv \
       --copy-bytes B OUT.txt --command "..."
@@ -23,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "cnn_fwd_bf16": ("cnn_fwd_bf16.hip", "cnn_common.hpp", "common.hpp"),
     "ms_step": ("ms_step.hip", "common.hpp"),
+    "cnn_bwd": ("cnn_bwd.hip", "cnn_common.hpp", "common.hpp"),
 }
 
 
@@ -107,6 +114,40 @@ def _traffic(args):
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
+def _sq(args):
+    vals = {}
+    for path in (args.a, args.b):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if args.kernel in r["Kernel_Name"]:
+                per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for k, v in per.items():
+            vals[k] = sum(v) / len(v)
+    n = args.nodes
+    simds = args.simds
+    act = vals["GRBM_GUI_ACTIVE"] / args.xcds
+    lines = ["SQ and GRBM counters of %s (%s)" % (args.kernel, args.what),
+             "command_a: " + args.command_a, "command_b: " + args.command_b,
+             "note: mean over the dispatches of the kernel; SQ wave-cycle counters are in units of 4 cycles; "
+             "%d XCDs x %d SIMDs" % (args.xcds, simds // args.xcds), ""]
+    lines += ["%s: %.6g" % (k, vals[k]) for k in sorted(vals)]
+    lines += ["", "derived:",
+              "valu_lane_op_slots_per_node: %.0f  (SQ_INSTS_VALU x 64 / nodes)" % (vals["SQ_INSTS_VALU"] * 64 / n),
+              "mfma_per_16_nodes: %.2f" % (vals["SQ_INSTS_MFMA"] * 16 / n),
+              "valu_cycles_per_simd: %.0f  (SQ_INSTS_VALU x 4 / %d SIMDs)" % (vals["SQ_INSTS_VALU"] * 4 / simds, simds),
+              "gpu_active_cycles_per_xcd: %.0f  (GRBM_GUI_ACTIVE / %d)" % (act, args.xcds),
+              "valu_busy_fraction: %.2f" % (vals["SQ_INSTS_VALU"] * 4 / simds / act),
+              "mfma_busy_fraction: %.2f  (SQ_VALU_MFMA_BUSY_CYCLES / %d SIMDs / active cycles)" % (
+                  vals["SQ_VALU_MFMA_BUSY_CYCLES"] / simds / act, simds),
+              "wave_time_waiting_on_waitcnt: %.2f  (SQ_WAIT_ANY / SQ_WAVE_CYCLES)" % (vals["SQ_WAIT_ANY"] / vals["SQ_WAVE_CYCLES"]),
+              "wave_time_issuing: %.2f  (SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES)" % (
+                  vals["SQ_ACTIVE_INST_ANY"] / vals["SQ_WAVE_CYCLES"]),
+              "wave_time_waiting_for_issue: %.2f  (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES)" % (
+                  vals["SQ_WAIT_INST_ANY"] / vals["SQ_WAVE_CYCLES"]),
+              "source_hash: %s" % source_hash(args.kind)]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -127,8 +168,20 @@ def main():
         t.add_argument("--" + k, required=True)
         t.add_argument("--command-" + k, required=True)
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    q = sub.add_parser("sq")
+    q.add_argument("out")
+    q.add_argument("--kind", choices=sorted(KERNEL_SOURCES), required=True)
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--what", default="")
+    q.add_argument("--nodes", type=int, required=True)
+    q.add_argument("--a", required=True)
+    q.add_argument("--b", required=True)
+    q.add_argument("--command-a", required=True)
+    q.add_argument("--command-b", required=True)
+    q.add_argument("--simds", type=int, default=1024)
+    q.add_argument("--xcds", type=int, default=8)
     a = ap.parse_args()
-    _stats(a) if a.cmd == "stats" else _traffic(a)
+    {"stats": _stats, "traffic": _traffic, "sq": _sq}[a.cmd](a)
 
 
 if __name__ == "__main__":
