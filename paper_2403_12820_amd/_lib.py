@@ -148,7 +148,14 @@ class Plan:
         L = lib()
         nb = C.c_size_t(0)
         check(L.pecnn_plan_device_bytes(C.byref(d), C.byref(nb)), "pecnn_plan_device_bytes")
-        self.pin = torch.as_tensor(np.ascontiguousarray(pin, np.uint8), device=device)
+        if isinstance(pin, torch.Tensor) and pin.is_cuda:
+            # already on the device (the plan keeps the reference; nothing is copied)
+            if pin.dtype != torch.uint8 or not pin.is_contiguous() or pin.numel() != int(np.sum(
+                    self._H.astype(np.int64) * self._W)):
+                raise ValueError("pin: a contiguous uint8 device tensor of one byte per node")
+            self.pin = pin
+        else:
+            self.pin = torch.as_tensor(np.ascontiguousarray(pin, np.uint8), device=device)
         self.mem = torch.empty(nb.value, dtype=torch.uint8, device=device)
         h = C.c_void_p()
         check(L.pecnn_plan_create(C.byref(d), _ptr(self.pin), _ptr(self.mem), nb.value, _stream(), C.byref(h)),

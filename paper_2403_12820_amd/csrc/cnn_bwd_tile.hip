@@ -43,6 +43,52 @@ __device__ __forceinline__ f32x4 lds4(const float* __restrict__ t, int row, int 
 // the wave; its lanes exchange values through it).
 __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
+// The per-lane operand tables, (table row r, lane l, u) at (r * 64 + l) * 4 + u: conv A operands
+// K (slots s = 4 sq + u), [A;B] A operands, [A^T | B^T] A operands and K^T A operands (row
+// kappa = 4 s + g' of the conv's K dimension). Loops of fixed trip count, so that the parameter
+// loads of a thread are all in flight together.
+template <int CH>
+__device__ __forceinline__ void fill_tables(float* lds, const float* __restrict__ theta, int tid) {
+  using Lc = BtLds<CH>;
+  constexpr int CPL = Lc::CPL, PL = Lc::PL, HX = Lc::HX;
+  const ThetaOff O = theta_off(CH);
+#pragma unroll
+  for (int k = 0; k < Lc::CONV_R; ++k) {
+    const int e = tid + 256 * k;
+    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
+    const int mb = r / 4, s = 4 * (r % 4) + u, lli = l & 15, lg = l >> 4;
+    int lo;
+    const int t = slot_tap(lg, s, PL, HX, lo);
+    lds[Lc::oCONV + e] = t >= 0 ? theta[O.K + (16 * mb + lli) * 54 + t] : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < Lc::MIX_R; ++k) {
+    const int e = tid + 256 * k;
+    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
+    const int mbp = r / (CPL / 4), ee = 4 * (r % (CPL / 4)) + u, lli = l & 15, lg = l >> 4;
+    lds[Lc::oMIX + e] = mix_weight<CH>(theta, O, 16 * mbp + lli, lg, ee);
+  }
+#pragma unroll
+  for (int k = 0; k < Lc::MIXT_R; ++k) {
+    const int e = tid + 256 * k;
+    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
+    const int mb = r / (2 * CPL / 4), jj = 4 * (r % (2 * CPL / 4)) + u, lli = l & 15, lg = l >> 4;
+    const int base = jj < CPL ? O.A : O.B;
+    const int c = slot_channel(lg, jj < CPL ? jj : jj - CPL);
+    lds[Lc::oMIXT + e] = theta[base + c * CH + 16 * mb + lli];
+  }
+#pragma unroll
+  for (int k = 0; k < Lc::KT_R; ++k) {
+    const int e = tid + 256 * k;
+    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
+    const int rb = r / (CPL / 4), ee = 4 * (r % (CPL / 4)) + u, lli = l & 15, lg = l >> 4;
+    const int kap = 16 * rb + lli;
+    int lo;
+    const int t = slot_tap(kap & 3, kap >> 2, PL, HX, lo);
+    lds[Lc::oKT + e] = t >= 0 ? theta[O.K + slot_channel(lg, ee) * 54 + t] : 0.f;
+  }
+}
+
 template <int CH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void bwd_tile_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
@@ -61,34 +107,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int li = lane & 15, g = lane >> 4;
   const ThetaOff O = theta_off(CH);
 
-  // per-lane operand tables (the same for every wave)
-  for (int e = tid; e < Lc::CONV_R * 256; e += 256) {
-    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
-    const int mb = r / 4, s = 4 * (r % 4) + u, lli = l & 15, lg = l >> 4;
-    int lo;
-    const int t = slot_tap(lg, s, PL, HX, lo);
-    lds[Lc::oCONV + e] = t >= 0 ? theta[O.K + (16 * mb + lli) * 54 + t] : 0.f;
-  }
-  for (int e = tid; e < Lc::MIX_R * 256; e += 256) {
-    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
-    const int mbp = r / (CPL / 4), ee = 4 * (r % (CPL / 4)) + u, lli = l & 15, lg = l >> 4;
-    lds[Lc::oMIX + e] = mix_weight<CH>(theta, O, 16 * mbp + lli, lg, ee);
-  }
-  for (int e = tid; e < Lc::MIXT_R * 256; e += 256) {
-    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
-    const int mb = r / (2 * CPL / 4), jj = 4 * (r % (2 * CPL / 4)) + u, lli = l & 15, lg = l >> 4;
-    const int base = jj < CPL ? O.A : O.B;
-    const int c = slot_channel(lg, jj < CPL ? jj : jj - CPL);
-    lds[Lc::oMIXT + e] = theta[base + c * CH + 16 * mb + lli];
-  }
-  for (int e = tid; e < Lc::KT_R * 256; e += 256) {
-    const int r = e >> 8, l = (e >> 2) & 63, u = e & 3;
-    const int rb = r / (CPL / 4), ee = 4 * (r % (CPL / 4)) + u, lli = l & 15, lg = l >> 4;
-    const int kap = 16 * rb + lli;  // slot index 4 s + g' of the conv's K dimension
-    int lo;
-    const int t = slot_tap(kap & 3, kap >> 2, PL, HX, lo);
-    lds[Lc::oKT + e] = t >= 0 ? theta[O.K + slot_channel(lg, ee) * 54 + t] : 0.f;
-  }
+  fill_tables<CH>(lds, theta, tid);
   __syncthreads();
 
   // LDS offsets of the im2col slots relative to the node's centre cell: the position slots

@@ -84,6 +84,16 @@ class WindowBatch:
         self.inst = torch.empty(n_win, dtype=torch.int32, device=device)
         self.frame = torch.empty(n_win, dtype=torch.int32, device=device)
         self.device = device
+        # Drawing a minibatch must not wait for the GPU to finish the previous iteration: the
+        # pins of every scene stay on the device (a minibatch's are gathered there), the window
+        # indices go up from two alternating pinned buffers, and the plan's small upload runs on
+        # a stream of its own.
+        self.pin_dev = torch.tensor(np.stack([s.pin for s in traj.scenes]), dtype=torch.uint8, device=device)
+        self.n_free_of = np.array([int((s.pin == 0).sum()) for s in traj.scenes], np.int64)
+        self._h_idx = [torch.empty(2, n_win, dtype=torch.int32).pin_memory() for _ in range(2)]
+        self._ev = [None, None]
+        self._slot = 0
+        self._side = torch.cuda.Stream(device=device)
 
     def sample(self, rng: np.random.Generator):
         """Draw windows uniformly over (scene, start frame); returns a plan for the minibatch."""
@@ -92,15 +102,28 @@ class WindowBatch:
         T = self.traj
         scenes = self.scene_ids[rng.integers(0, len(self.scene_ids), self.n_win)]
         k0 = rng.integers(0, T.n_frames - (self.n_unroll + 1), self.n_win).astype(np.int32)
-        self.inst.copy_(torch.from_numpy(scenes.astype(np.int32)))
-        self.frame.copy_(torch.from_numpy(k0))
+        main = torch.cuda.current_stream()
+        slot = self._slot
+        self._slot ^= 1
+        if self._ev[slot] is not None:
+            self._ev[slot].synchronize()  # the upload that last read this pinned buffer has run
+        h = self._h_idx[slot]
+        h[0].copy_(torch.from_numpy(scenes.astype(np.int32)))
+        h[1].copy_(torch.from_numpy(k0))
+        self.inst.copy_(h[0], non_blocking=True)
+        self.frame.copy_(h[1], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(main)
+        self._ev[slot] = ev
         L.pecnn_gather_windows(T.frames, T.batch.total, T.n_frames, T.off, T.batch.n, self.inst, self.frame,
                                self.n_win, self.npw, self.n_unroll + 2, self.buf)
+        pins = self.pin_dev.index_select(0, self.inst).reshape(-1)
         sc = [T.scenes[int(b)] for b in scenes]
-        pins = np.concatenate([s.pin for s in sc])
-        plan = L.Plan([s.H for s in sc], [s.W for s in sc], [s.h for s in sc], [s.mass for s in sc],
-                      np.array([s.a_ext for s in sc], np.float32), pins, self.device)
-        return plan, int((pins == 0).sum())
+        with torch.cuda.stream(self._side):
+            plan = L.Plan([s.H for s in sc], [s.W for s in sc], [s.h for s in sc], [s.mass for s in sc],
+                          np.array([s.a_ext for s in sc], np.float32), pins, self.device)
+        plan.mem.record_stream(main)  # allocated on the side stream, read by the main stream's kernels
+        return plan, int(self.n_free_of[scenes].sum())
 
 
 class Trainer:
