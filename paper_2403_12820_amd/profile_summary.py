@@ -9,11 +9,12 @@
       rates: VALU lane-op slots per node, MFMA per 16 nodes, VALU and MFMA busy fractions and
       where the waves spend their time.
 
-  python -m paper_2403_12820_amd.profile_summary traffic --kernel NAME --nodes N \
+  python -m paper_2403_12820_amd.profile_summary traffic --kernel NAME[,NAME...] --nodes N \
       --fetch FETCH.csv --write WRITE.csv --copy-fetch CF.csv --copy-write CW.csv \
-      --copy-bytes B OUT.txt --command "..."
-      HBM bytes per launch of one kernel from two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
-      dispatch), each scaled by what the same counter reads for a plain device copy of B bytes.
+      --copy-bytes B OUT.txt --command-fetch "..." (and the other three commands)
+      HBM bytes per launch of one kernel (or of each of several) from two --pmc runs (FETCH_SIZE,
+      WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a plain device
+      copy of B bytes.
 
 The traffic summary carries a hash of the kernel's sources; bench.py reports its figure only
 while the sources still hash the same.
@@ -83,34 +84,52 @@ def _per_dispatch(path: str, name: str, counter: str):
 
 
 def _traffic(args):
-    f_kib, nf = _per_dispatch(args.fetch, args.kernel, "FETCH_SIZE")
-    w_kib, nw = _per_dispatch(args.write, args.kernel, "WRITE_SIZE")
     # the copy kernel: take its largest dispatch (the 1 GiB copy)
     cf = max(float(r["Counter_Value"]) for r in csv.DictReader(open(args.copy_fetch)) if r["Counter_Name"] == "FETCH_SIZE")
     cw = max(float(r["Counter_Value"]) for r in csv.DictReader(open(args.copy_write)) if r["Counter_Name"] == "WRITE_SIZE")
     kf, kw = args.copy_bytes / (cf * 1024), args.copy_bytes / (cw * 1024)
-    fetch_b, write_b = f_kib * 1024 * kf, w_kib * 1024 * kw
-    lines = [
-        "HBM traffic per launch of %s (rocprofv3 --pmc)" % args.kernel,
+    kernels = args.kernel.split(",")
+    head = [
         "command_fetch: " + args.command_fetch,
         "command_write: " + args.command_write,
         "command_copy_fetch: " + args.command_copy_fetch,
         "command_copy_write: " + args.command_copy_write,
-        "kernel: %s" % args.kernel,
-        "nodes: %d" % args.nodes,
-        "dispatches: %d fetch, %d write" % (nf, nw),
-        "fetch_kib_per_dispatch: %.1f" % f_kib,
-        "write_kib_per_dispatch: %.1f" % w_kib,
+    ]
+    calib = [
         "copy_calibration: a %d-byte device copy reads FETCH_SIZE %.1f KiB and WRITE_SIZE %.1f KiB" % (
             args.copy_bytes, cf, cw),
         "fetch_factor: %.4f" % kf,
         "write_factor: %.4f" % kw,
-        "fetch_bytes: %.0f" % fetch_b,
-        "write_bytes: %.0f" % write_b,
-        "bytes_per_launch: %.0f" % (fetch_b + write_b),
-        "bytes_per_node: %.2f" % ((fetch_b + write_b) / args.nodes),
-        "source_hash: %s" % source_hash(args.kind),
     ]
+    if len(kernels) == 1:
+        f_kib, nf = _per_dispatch(args.fetch, args.kernel, "FETCH_SIZE")
+        w_kib, nw = _per_dispatch(args.write, args.kernel, "WRITE_SIZE")
+        fetch_b, write_b = f_kib * 1024 * kf, w_kib * 1024 * kw
+        lines = ["HBM traffic per launch of %s (rocprofv3 --pmc)" % args.kernel] + head + [
+            "kernel: %s" % args.kernel,
+            "nodes: %d" % args.nodes,
+            "dispatches: %d fetch, %d write" % (nf, nw),
+            "fetch_kib_per_dispatch: %.1f" % f_kib,
+            "write_kib_per_dispatch: %.1f" % w_kib,
+        ] + calib + [
+            "fetch_bytes: %.0f" % fetch_b,
+            "write_bytes: %.0f" % write_b,
+            "bytes_per_launch: %.0f" % (fetch_b + write_b),
+            "bytes_per_node: %.2f" % ((fetch_b + write_b) / args.nodes),
+        ]
+    else:
+        lines = ["HBM traffic per launch of each kernel of %s on %d nodes (rocprofv3 --pmc FETCH_SIZE and "
+                 "WRITE_SIZE, each scaled by the same counter on a plain device copy)" % (args.what or args.kind,
+                                                                                         args.nodes)] + head + calib
+        total = 0.0
+        for k in kernels:
+            f_kib, _ = _per_dispatch(args.fetch, k, "FETCH_SIZE")
+            w_kib, _ = _per_dispatch(args.write, k, "WRITE_SIZE")
+            fb, wb = f_kib * 1024 * kf, w_kib * 1024 * kw
+            total += fb + wb
+            lines.append("%s: fetch %.0f B, write %.0f B, %.1f B per node" % (k, fb, wb, (fb + wb) / args.nodes))
+        lines.append("bytes_per_node_all_kernels: %.1f" % (total / args.nodes))
+    lines += ["note: " + n for n in args.note] + ["source_hash: %s" % source_hash(args.kind)]
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
@@ -168,6 +187,8 @@ def main():
         t.add_argument("--" + k, required=True)
         t.add_argument("--command-" + k, required=True)
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    t.add_argument("--what", default="", help="workload named in the header of a several-kernel summary")
+    t.add_argument("--note", action="append", default=[], help="a line of context (repeatable)")
     q = sub.add_parser("sq")
     q.add_argument("out")
     q.add_argument("--kind", choices=sorted(KERNEL_SOURCES), required=True)
