@@ -102,7 +102,9 @@ static int check_plan(const pecnn_plan* plan) {
 
 // ---------------------------------------------------------------- rollout graph cache
 struct GraphKey {
-  const void* buf[4];
+  const void* buf[2];       // the caller's s_prev, s_cur (the other states live in ws)
+  int pi, ci;               // states S^{k-1}, S^k of the chunk's first frame (indices, see rollout)
+  int pre_len, pre_code;    // leading frames of the chunk that follow the prefix schedule
   int len, with_ms, guard, ms_cfg, cnn_cfg, ch, prec, cell, substeps;
   float dt, alpha;
   const float* theta;
@@ -205,6 +207,7 @@ __global__ __launch_bounds__(256) void take_tripped_kernel(const InstDev* __rest
 
 struct RolloutWs {
   float* X;        // third rotating state
+  float* Y;        // fourth rotating state (the prefix schedule)
   float* T;        // mass-spring substep temporary
   double* part;    // reduction partials
   double* now;     // [4n] diagnostics of the current check
@@ -224,6 +227,7 @@ static RolloutWs rollout_layout(const pecnn_plan* plan, void* base) {
   size_t o = 0;
   const size_t st = align256(6 * (size_t)plan->total * sizeof(float));
   w.X = (float*)(p + o); o += st;
+  w.Y = (float*)(p + o); o += st;
   w.T = (float*)(p + o); o += st;
   w.part = (double*)(p + o); o += align256(reduce_ws_bytes(plan));
   w.now = (double*)(p + o); o += align256(4 * (size_t)plan->n * sizeof(double));
@@ -670,29 +674,44 @@ int pecnn_gather_windows(const float* traj, int64_t traj_nodes, int32_t n_saved,
 }
 
 // ---------------------------------------------------------------- rollout
-// Record the network steps of one chunk (and the guard check that ends it) on 'st'. With the
-// frame-error test on, the simulator's answer for the chunk's last frame is written into the
-// third buffer, which after the last rotation holds nothing the rollout still needs (the next
-// frame overwrites it).
+// The rollout rotates four device states: the caller's s_prev and s_cur (indices 0 and 1) and
+// X, Y in the workspace (2 and 3). Frame k reads S^{k-1}, S^k and writes S^{k+1} into a state
+// holding neither. The three-state cycle (write the one of 0, 1, 2 not read) returns S^{n-1},
+// S^n to indices 0, 1 every 3 frames, the four-state cycle 2, 3, 0, 1 every 4, so a call of
+// n = 3i + 4j frames starts with j four-state cycles and needs no copy at the end (every n but
+// 1, 2 and 5).
+static int rollout_prefix(int n) {
+  if (n % 3 == 1 && n >= 4) return 4;
+  if (n % 3 == 2 && n >= 8) return 8;
+  return 0;
+}
+static int rollout_dest(int k, int prefix, int pi, int ci) {
+  static const int c4[4] = {2, 3, 0, 1};
+  return k < prefix ? c4[k & 3] : 3 - pi - ci;
+}
+
+// Record the network steps of one chunk (frames k0 .. k0 + len - 1 of the call, starting from
+// states pi, ci) and the guard check that ends it, on 'st'. With the frame-error test on, the
+// simulator's answer for the chunk's last frame is written into the state the next frame would
+// write, which holds nothing the rollout still needs.
 static int record_chunk(pecnn_plan* p, const pecnn_model* m, const MsParamsDev& sim, const pecnn_guard* g,
-                        float* const buf[3], float* T, int len, bool with_ms, bool guard_on, int32_t* fallback,
-                        double* stats, const RolloutWs& w, hipStream_t st) {
-  float* P = buf[0];
-  float* C = buf[1];
-  float* X = buf[2];
-  for (int k = 0; k < len; ++k) {
-    int rc = cnn_forward_launch(p, p->cnn_cfg, m, P, C, X, fallback, st);
+                        float* const B[4], int pi, int ci, int k0, int prefix, float* T, int len, bool with_ms,
+                        bool guard_on, int32_t* fallback, double* stats, const RolloutWs& w, hipStream_t st) {
+  for (int k = k0; k < k0 + len; ++k) {
+    const int di = rollout_dest(k, prefix, pi, ci);
+    int rc = cnn_forward_launch(p, p->cnn_cfg, m, B[pi], B[ci], B[di], fallback, st);
     if (rc) return rc;
     if (with_ms) {
-      rc = ms_step_run(p, p->ms_cfg, sim, C, X, T, g->substeps, w.active, st);
+      rc = ms_step_run(p, p->ms_cfg, sim, B[ci], B[di], T, g->substeps, w.active, st);
       if (rc) return rc;
     }
-    float* t = P;
-    P = C;
-    C = X;
-    X = t;
+    pi = ci;
+    ci = di;
   }
   if (guard_on) {
+    float* P = B[pi];
+    float* C = B[ci];
+    float* X = B[rollout_dest(k0 + len, prefix, pi, ci)];
     const bool ferr = g->frame_err_max > 0.f;
     if (ferr) {
       int rc = ms_step_run(p, p->ms_cfg, sim, P, X, T, g->substeps, nullptr, st);
@@ -770,7 +789,9 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     PECNN_HIP(hipStreamSynchronize(st));
   }
 
-  float* buf[3] = {s_prev, s_cur, w.X};
+  float* const B[4] = {s_prev, s_cur, w.X, w.Y};
+  const int prefix = rollout_prefix(n_steps);
+  int pi = 0, ci = 1;
   int k = 0;
   const int chunk = guard_on ? g->check_every : n_steps;
   while (k < n_steps) {
@@ -778,7 +799,11 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     const bool with_ms = *gc->host_count > 0;
     GraphKey key;
     memset(&key, 0, sizeof(key));
-    key.buf[0] = buf[0]; key.buf[1] = buf[1]; key.buf[2] = buf[2]; key.buf[3] = w.T;
+    key.buf[0] = s_prev; key.buf[1] = s_cur; key.pi = pi; key.ci = ci;
+    for (int i = 0; i < len && k + i < prefix; ++i) {
+      key.pre_len = i + 1;
+      key.pre_code |= rollout_dest(k + i, prefix, 0, 0) << (2 * i);
+    }
     key.len = len; key.with_ms = with_ms; key.guard = guard_on; key.ms_cfg = p->ms_cfg; key.cnn_cfg = p->cnn_cfg;
     key.ch = m->ch; key.prec = m->precision; key.cell = m->cell; key.substeps = g->substeps; key.dt = m->dt; key.alpha = m->isru_alpha;
     key.theta = m->theta; key.sim = *simp; key.gd = *g; key.fallback = fallback; key.ws = ws;
@@ -789,7 +814,8 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     if (!exec) {
       hipGraph_t graph;
       PECNN_HIP(hipStreamBeginCapture(gc->capture, hipStreamCaptureModeThreadLocal));
-      rc = record_chunk(p, m, sim, g, buf, w.T, len, with_ms, guard_on, fallback, stats_d, w, gc->capture);
+      rc = record_chunk(p, m, sim, g, B, pi, ci, k, prefix, w.T, len, with_ms, guard_on, fallback, stats_d, w,
+                        gc->capture);
       hipError_t e2 = hipStreamEndCapture(gc->capture, &graph);
       if (rc) {
         if (e2 == hipSuccess) (void)hipGraphDestroy(graph);
@@ -807,10 +833,9 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     }
     PECNN_HIP(hipGraphLaunch(exec, st));
     for (int i = 0; i < len; ++i) {
-      float* t = buf[0];
-      buf[0] = buf[1];
-      buf[1] = buf[2];
-      buf[2] = t;
+      const int di = rollout_dest(k + i, prefix, pi, ci);
+      pi = ci;
+      ci = di;
     }
     k += len;
     if (guard_on && k < n_steps) {
@@ -818,14 +843,15 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
       PECNN_HIP(hipStreamSynchronize(st));
     }
   }
-  // hand the last two states back in the caller's buffers
-  if (buf[0] != s_prev || buf[1] != s_cur) {
-    if (buf[0] == s_cur) {  // (s_cur, X)
+  // hand the last two states back in the caller's buffers (only n = 1, 2, 5 end elsewhere; the
+  // three-state cycle then leaves them at (1, 2) or (2, 0))
+  if (pi != 0 || ci != 1) {
+    if (pi == 1) {  // (s_cur, X)
       PECNN_HIP(hipMemcpyAsync(s_prev, s_cur, sb, hipMemcpyDeviceToDevice, st));
-      PECNN_HIP(hipMemcpyAsync(s_cur, w.X, sb, hipMemcpyDeviceToDevice, st));
+      PECNN_HIP(hipMemcpyAsync(s_cur, B[ci], sb, hipMemcpyDeviceToDevice, st));
     } else {  // (X, s_prev)
       PECNN_HIP(hipMemcpyAsync(s_cur, s_prev, sb, hipMemcpyDeviceToDevice, st));
-      PECNN_HIP(hipMemcpyAsync(s_prev, w.X, sb, hipMemcpyDeviceToDevice, st));
+      PECNN_HIP(hipMemcpyAsync(s_prev, B[pi], sb, hipMemcpyDeviceToDevice, st));
     }
   }
   return PECNN_OK;
