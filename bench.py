@@ -27,7 +27,10 @@ Printed (one JSON line): the contract fields, plus
                   simulator over the same simulated time; rms_within_bound is decided there.
 
 Before the timed region the graphs of the rollout are captured by an untimed run of the same
-length (the library caches one graph per chunk length, buffer rotation and fall-back mix).
+length (the library caches one graph per chunk length, buffer rotation and fall-back mix), and
+further untimed runs of that length follow for --settle-s seconds (default 0.3), so that the
+timed frames see the clock the chip holds under sustained load (the number of untimed frames is
+reported in config).
 --profile KIND launches one kernel a fixed number of times instead (for counter runs).
 
 --cell pair runs section 3.2's own cell read literally instead (twelve frozen
@@ -260,6 +263,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--settle-s", type=float, default=0.3,
+                    help="untimed rollouts of the timed length after the warm-up, for at least this long")
     ap.add_argument("--workload", choices=("uniform", "batched"), default="uniform",
                     help="uniform: INSTANCES cloths of SIZE x SIZE; batched: 512 cloths with sides drawn "
                          "log-uniform in [16, 256] (seed 2)")
@@ -362,6 +367,19 @@ def main():
         fb.copy_(fb0)
         L.pecnn_rollout(plan, model, sim, guard, a, b, frames, fb, stats, ws)
         torch.cuda.synchronize()
+    # ---- untimed: the same rollout again until the chip has been under this load for --settle-s
+    # seconds. Its clock ramps under sustained load: the same frame launch takes about 20% longer
+    # in the first tens of milliseconds than after a few tenths of a second, so without this the
+    # timed frames would measure the ramp rather than the rate a running rollout holds
+    untimed = args.warmup + args.steps
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < args.settle_s:
+        a.copy_(s0)
+        b.copy_(s0)
+        fb.copy_(fb0)
+        L.pecnn_rollout(plan, model, sim, guard, a, b, args.steps, fb, stats, ws)
+        torch.cuda.synchronize()
+        untimed += args.steps
     a.copy_(s0)
     b.copy_(s0)
     fb.copy_(fb0)
@@ -482,6 +500,7 @@ def main():
                         "frames" % ("FP32 pair-cell (the paper's own cell, 12 channels)" if pair else
                                     "bf16 CNN (Ch=%d)" % ch, workload, args.steps, stride, args.check_every),
             "cell": args.cell,
+            "untimed_frames_before_timing": untimed, "settle_s": args.settle_s,
             "instances": batch.n, "grid": ([args.size, args.size] if args.workload == "uniform" else
                                           [int(batch.H.min()), int(batch.H.max())]),
             "nodes": N, "channels": ch,

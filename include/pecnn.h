@@ -220,8 +220,11 @@ typedef struct {
    network's frame that the check judged, before the simulator's frame replaces it.
    ws: pecnn_workspace_bytes(plan, model, PECNN_WS_ROLLOUT). The steps between checks run as
    one captured HIP graph (cached in the plan per buffer set). The host reads the fallback
-   count at the start and after every check but the last, so the call synchronises 'stream'
-   that often; it returns with the last graph still queued. */
+   count at the start (waiting for the stream) and after every check but the last; it reads a
+   check's count after launching the chunk that follows it, so it waits only for work queued
+   before that chunk. A chunk launched before the first instances fell back is completed for
+   them afterwards by the mass-spring steps alone. The call returns with the last chunk still
+   queued. */
 int pecnn_rollout(pecnn_plan* plan, const pecnn_model* model, const cloth_ms_params* sim,
                   const pecnn_guard* guard, float* s_prev, float* s_cur, int32_t n_steps,
                   int32_t* fallback, double* stats, void* ws, size_t ws_bytes, void* stream);

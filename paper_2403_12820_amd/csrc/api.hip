@@ -122,7 +122,8 @@ struct GraphEntry {
 struct GraphCache {
   std::vector<GraphEntry> entries;
   hipStream_t capture = nullptr;
-  int* host_count = nullptr;
+  int* host_count = nullptr;           // [2] pinned: fallen instances after a check, two in flight
+  hipEvent_t count_ready[2] = {nullptr, nullptr};
 };
 
 static void graph_cache_free(pecnn_plan* plan) {
@@ -131,6 +132,8 @@ static void graph_cache_free(pecnn_plan* plan) {
   for (auto& e : gc->entries) (void)hipGraphExecDestroy(e.exec);
   if (gc->capture) (void)hipStreamDestroy(gc->capture);
   if (gc->host_count) (void)hipHostFree(gc->host_count);
+  for (hipEvent_t e : gc->count_ready)
+    if (e) (void)hipEventDestroy(e);
   delete gc;
   plan->graph_cache = nullptr;
 }
@@ -142,27 +145,31 @@ static void graph_cache_free(pecnn_plan* plan) {
 // simulator's frame times escale = 1 / (nodes width^2) with the squared bound; a tripped
 // instance falls back for good. Also counts fallen instances.
 // count[0] receives the number of fallen instances, count[1] keeps the index of the check.
+// mode 0: a check; 1: the prologue (starting energy and stretch, no test); 2: the diagnostics of
+// the last check taken again from a repaired state (no test, same check index). len: frames of
+// the chunk the check ends (all chunks but a call's last have check_every).
 __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restrict__ now, double* __restrict__ e0,
                                                     const double* __restrict__ eref,
-                                                    const double* __restrict__ escale, pecnn_guard G, int init,
+                                                    const double* __restrict__ escale, pecnn_guard G, int mode,
+                                                    int len,
                                                     int32_t* __restrict__ fallback, uint8_t* __restrict__ active_ms,
                                                     uint8_t* __restrict__ tripped, double* __restrict__ stats,
                                                     int* __restrict__ count) {
   __shared__ int sh[256];
-  const int chk = init ? 0 : count[1] + 1;
-  const int step = chk * G.check_every;
+  const int chk = mode == 1 ? 0 : (mode == 2 ? count[1] : count[1] + 1);
+  const int step = (chk - 1) * G.check_every + len;  // frames since the call began
   const bool ferr = G.frame_err_max > 0.f;
   const double ferr2 = (double)G.frame_err_max * (double)G.frame_err_max;
   int cnt = 0;
   for (int b = threadIdx.x; b < n; b += 256) {
     const double e = now[4 * b + 1], st = now[4 * b + 2];
-    tripped[b] = 0;
-    if (init) {
+    if (mode != 2) tripped[b] = 0;
+    if (mode == 1) {
       e0[b] = e;
       stats[4 * b + 0] = e;
       stats[4 * b + 2] = st;
       stats[4 * b + 3] = fallback[b] ? 0.0 : -1.0;
-    } else if (fallback[b] == 0 &&
+    } else if (mode == 0 && fallback[b] == 0 &&
                (!(st <= (double)G.stretch_max) ||
                 (isfinite(eref[b]) && !((e - e0[b]) / eref[b] <= (double)G.energy_gain_max)) ||
                 (ferr && !(now[4 * b] * escale[b] <= ferr2)))) {
@@ -185,6 +192,13 @@ __global__ __launch_bounds__(256) void guard_kernel(int n, const double* __restr
     count[0] = sh[0];
     count[1] = chk;
   }
+}
+
+// active[b] = instance b fell back before the last check (fallen, but not at that check).
+__global__ __launch_bounds__(256) void late_mask_kernel(int n, const int32_t* __restrict__ fallback,
+                                                        const uint8_t* __restrict__ tripped,
+                                                        uint8_t* __restrict__ active) {
+  for (int b = threadIdx.x; b < n; b += 256) active[b] = fallback[b] != 0 && tripped[b] == 0;
 }
 
 // Copies the six state planes of every instance flagged in 'tripped' from src to dst (one
@@ -719,7 +733,7 @@ static int record_chunk(pecnn_plan* p, const pecnn_model* m, const MsParamsDev& 
     }
     int rc = reduce_launch(p, sim, C, ferr ? X : nullptr, w.now, w.part, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 0,
+    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 0, len,
                        fallback, w.active, w.tripped, stats, w.count);
     PECNN_LAUNCH_CHECK("guard_kernel");
     if (ferr) {  // an instance that fell back here takes the simulator's frame instead of the network's
@@ -727,6 +741,33 @@ static int record_chunk(pecnn_plan* p, const pecnn_model* m, const MsParamsDev& 
                          p->d_prefix[kCfgChunk], p->d_chunk_inst, p->total, w.tripped, X, C);
       PECNN_LAUNCH_CHECK("take_tripped_kernel");
     }
+  }
+  return PECNN_OK;
+}
+
+// Repair of a chunk that ran without the mass-spring steps although instances had fallen back at
+// the check before it (see pecnn_rollout): the frame kernels skipped those instances, so their
+// frames are computed here by the mass-spring steps alone, in the chunk's buffer order; then the
+// diagnostics of the chunk's own check are taken again for every instance. The instances that
+// tripped at that check itself ran the network through the chunk and are left alone.
+static int repair_chunk(pecnn_plan* p, const MsParamsDev& sim, const pecnn_guard* g, float* const B[4], int pi,
+                        int ci, int k0, int prefix, float* T, int len, bool guard_on, int32_t* fallback,
+                        double* stats, const RolloutWs& w, hipStream_t st) {
+  hipLaunchKernelGGL(late_mask_kernel, dim3(1), dim3(256), 0, st, p->n, fallback, w.tripped, w.active);
+  PECNN_LAUNCH_CHECK("late_mask_kernel");
+  for (int k = k0; k < k0 + len; ++k) {
+    const int di = rollout_dest(k, prefix, pi, ci);
+    int rc = ms_step_run(p, p->ms_cfg, sim, B[ci], B[di], T, g->substeps, w.active, st);
+    if (rc) return rc;
+    pi = ci;
+    ci = di;
+  }
+  if (guard_on) {
+    int rc = reduce_launch(p, sim, B[ci], nullptr, w.now, w.part, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 2, len,
+                       fallback, w.active, w.tripped, stats, w.count);
+    PECNN_LAUNCH_CHECK("guard_kernel");
   }
   return PECNN_OK;
 }
@@ -763,7 +804,8 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     gc = new GraphCache();
     p->graph_cache = gc;
     PECNN_HIP(hipStreamCreateWithFlags(&gc->capture, hipStreamNonBlocking));
-    PECNN_HIP(hipHostMalloc((void**)&gc->host_count, sizeof(int), hipHostMallocDefault));
+    PECNN_HIP(hipHostMalloc((void**)&gc->host_count, 2 * sizeof(int), hipHostMallocDefault));
+    for (hipEvent_t& e : gc->count_ready) PECNN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
 
   // prologue: energy scale, starting diagnostics, fall-back mask
@@ -782,11 +824,12 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
     PECNN_HIP(hipMemcpyAsync(w.escale, escale.data(), sizeof(double) * p->n, hipMemcpyHostToDevice, st));
     rc = reduce_launch(p, sim, s_cur, nullptr, w.now, w.part, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 1,
+    hipLaunchKernelGGL(guard_kernel, dim3(1), dim3(256), 0, st, p->n, w.now, w.e0, w.eref, w.escale, *g, 1, 0,
                        fallback, w.active, w.tripped, stats_d, w.count);
     PECNN_LAUNCH_CHECK("guard_kernel");
-    PECNN_HIP(hipMemcpyAsync(gc->host_count, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
-    PECNN_HIP(hipStreamSynchronize(st));
+    PECNN_HIP(hipMemcpyAsync(&gc->host_count[0], w.count, sizeof(int), hipMemcpyDeviceToHost, st));
+    PECNN_HIP(hipEventRecord(gc->count_ready[0], st));
+    PECNN_HIP(hipEventSynchronize(gc->count_ready[0]));
   }
 
   float* const B[4] = {s_prev, s_cur, w.X, w.Y};
@@ -794,9 +837,19 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
   int pi = 0, ci = 1;
   int k = 0;
   const int chunk = guard_on ? g->check_every : n_steps;
+  // The host runs one chunk ahead of the fall-back count it has read: after the first chunk
+  // (decided by the prologue's count), a chunk is launched with or without the mass-spring steps
+  // of fallen instances according to the last count known on the host, and the count of the
+  // check before it is read only after the launch, so the GPU does not wait for the host. If
+  // that count shows the first instances fallen while the chunk was launched without the
+  // mass-spring steps, the chunk skipped them (the frame kernels skip fallen instances), and
+  // repair_chunk computes their frames.
+  bool any_fallen = gc->host_count[0] > 0;  // last count read on the host was nonzero
+  int pending = -1;                          // host slot of a count not yet read
+  int nchunk = 0;
   while (k < n_steps) {
     const int len = chunk < n_steps - k ? chunk : n_steps - k;
-    const bool with_ms = *gc->host_count > 0;
+    const bool with_ms = any_fallen;
     GraphKey key;
     memset(&key, 0, sizeof(key));
     key.buf[0] = s_prev; key.buf[1] = s_cur; key.pi = pi; key.ci = ci;
@@ -832,16 +885,30 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
       gc->entries.push_back(GraphEntry{key, exec});
     }
     PECNN_HIP(hipGraphLaunch(exec, st));
+    const int k0 = k, pi0 = pi, ci0 = ci;
     for (int i = 0; i < len; ++i) {
       const int di = rollout_dest(k + i, prefix, pi, ci);
       pi = ci;
       ci = di;
     }
     k += len;
-    if (guard_on && k < n_steps) {
-      PECNN_HIP(hipMemcpyAsync(gc->host_count, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
-      PECNN_HIP(hipStreamSynchronize(st));
+    int next = -1;
+    if (guard_on && k < n_steps) {  // this chunk's count, read after the next chunk's launch
+      next = nchunk & 1;
+      PECNN_HIP(hipMemcpyAsync(&gc->host_count[next], w.count, sizeof(int), hipMemcpyDeviceToHost, st));
+      PECNN_HIP(hipEventRecord(gc->count_ready[next], st));
     }
+    if (pending >= 0) {  // the previous chunk's count
+      PECNN_HIP(hipEventSynchronize(gc->count_ready[pending]));
+      const bool fallen = gc->host_count[pending] > 0;
+      if (fallen && !with_ms) {
+        rc = repair_chunk(p, sim, g, B, pi0, ci0, k0, prefix, w.T, len, guard_on, fallback, stats_d, w, st);
+        if (rc) return rc;
+      }
+      any_fallen = any_fallen || fallen;
+    }
+    pending = next;
+    ++nchunk;
   }
   // hand the last two states back in the caller's buffers (only n = 1, 2, 5 end elsewhere; the
   // three-state cycle then leaves them at (1, 2) or (2, 0))

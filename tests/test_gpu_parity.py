@@ -420,6 +420,53 @@ def test_rollout_forced_fallback_matches_mass_spring(torch_mod, L):
     assert np.array_equal(a.cpu().numpy(), prev.cpu().numpy())
 
 
+@pytest.mark.parametrize("n", [7, 8, 10])
+def test_rollout_partial_trip_at_a_later_check(torch_mod, L, n):
+    """One cloth trips at the second check (frame 6), the other at frame 8 (the last, shorter
+    chunk of an 8-frame call) or 9: the chunk after a trip is launched before the host has read
+    that check's count, so the fallen cloth's frames there come from the repair (mass-spring
+    steps alone in the chunk's buffer order). Each cloth must equal its own reference: network
+    frames up to its trip, then 'sub' mass-spring steps per frame; the recorded step of each
+    fall-back is the frame of its check."""
+    torch = torch_mod
+    every, sub, bound = 3, 4, 2.05
+    batch, plan, model, s0, s1 = _rollout_setup(L, torch, [(24, 40), (9, 9)], 1100)
+    # the FP64 oracle's largest structural stretch per frame puts the checks clear of the bound:
+    # frame 3: both below; frame 6: cloth 0 above, cloth 1 below; frame 9: cloth 1 above
+    th = model._theta_ref.cpu().numpy()
+    P, C = s0.astype(np.float64), s1.astype(np.float64)
+    stretch = {}
+    for k in range(1, 10):
+        P, C = C, oracle.batch_cnn_forward(batch, 32, 1.0, 5e-3, th, P, C)[0]
+        stretch[k] = [oracle.max_stretch(batch.H[b], batch.W[b], batch.h[b], C[:, batch.instance(b)]) for b in (0, 1)]
+    assert max(stretch[3]) < bound / 1.05 and stretch[6][0] > bound * 1.05 and stretch[6][1] < bound / 1.05
+    assert stretch[7][1] < bound / 1.02 and min(stretch[8][1], stretch[9][1]) > bound * 1.05
+    trip = {0: 6, 1: {7: None, 8: 8, 10: 9}[n]}
+    sim = L.ms_params(MAT)
+    a, b = dev_tensor(s0), dev_tensor(s1)
+    fb = torch.zeros(batch.n, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(4 * batch.n, dtype=torch.float64, device="cuda")
+    L.pecnn_rollout(plan, model, sim, _guard(L, stretch=bound, gain=1e30, every=every, sub=sub), a, b, n, fb, stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy().reshape(-1, 4)
+    for c in (0, 1):
+        assert fb.cpu().numpy()[c] == (trip[c] is not None)
+        assert st[c, 3] == (trip[c] if trip[c] is not None else -1)
+    got_p, got_c = a.cpu().numpy(), b.cpu().numpy()
+    for c in (0, 1):
+        m = trip[c] if trip[c] is not None else n  # network frames (a trip at the last check changes no frame)
+        rp, rc = _forward_loop(L, torch, plan, model, s0, s1, m)
+        cur, prev = dev_tensor(rc), dev_tensor(rp)
+        for _ in range(n - m):
+            nxt = torch.zeros_like(cur)
+            L.cloth_ms_step(plan, sim, cur, nxt, sub)
+            prev, cur = cur, nxt
+        torch.cuda.synchronize()
+        sl = batch.instance(c)
+        assert np.array_equal(got_c[:, sl], cur.cpu().numpy()[:, sl])
+        assert np.array_equal(got_p[:, sl], prev.cpu().numpy()[:, sl])
+
+
 def test_rollout_preset_fallback_instance(torch_mod, L):
     """A caller-preset flag sends that instance to the mass-spring step from the first frame while
     the others keep the network."""
