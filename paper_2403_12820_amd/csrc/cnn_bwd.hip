@@ -10,6 +10,7 @@
 //     Accumulates into g_cur and g_prev.
 //  3. wgrad_final: a fixed-order sum of the partial rows into g_theta.
 // The pair cell (section 3.2 read literally) and the sphere's reverse mode follow below.
+#include "cnn_bwd_table.hpp"
 #include "cnn_common.hpp"
 
 namespace pecnn {

@@ -16,6 +16,7 @@
 //     their sums in LDS and the workgroup writes one row of partial sums.
 // Deterministic: every wave owns fixed segments and sums them in order, the waves are added in
 // order, and the rows are summed in order by the final kernel.
+#include "cnn_bwd_table.hpp"
 #include "cnn_common.hpp"
 
 namespace pecnn {

@@ -30,14 +30,6 @@ __device__ __forceinline__ int slot_tap(int g, int s, int PL, int HX, int& lds_o
 // Channel held in D-layout slot e (0..Ch/4-1) by lane group g.
 __device__ __forceinline__ int slot_channel(int g, int e) { return 16 * (e >> 2) + 4 * g + (e & 3); }
 
-// Node-blocked table written by the reverse pass and read by its gather kernel: per node the
-// adjoints of the im2col entries of U(S^k) (through both U(S^k) and U(S^k - S^{k-1})) and of
-// U(S^k - S^{k-1}), 54 rows each in tap order c * 9 + o, then gdv = dLoss/d(dv) (3 rows). 32
-// consecutive nodes form one block of rows x 32 floats.
-constexpr int kBtRows = 111, kBtGus = 0, kBtGud = 54, kBtGdv = 108;
-__host__ __device__ inline int64_t bt_node(int64_t q) { return (q >> 5) * (int64_t)kBtRows * 32 + (q & 31); }
-__host__ __device__ inline int64_t bt_floats(int64_t n) { return (n + 31) / 32 * 32 * (int64_t)kBtRows; }
-
 __device__ __forceinline__ float isru(float z, float alpha) {
   return z * __builtin_amdgcn_rsqf(__builtin_fmaf(alpha * z, z, 1.f));
 }
