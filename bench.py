@@ -19,7 +19,10 @@ Printed (one JSON line): the contract fields, plus
                   work per node (alu_ops_per_node) over the lane-operation peak, with the HBM
                   view (algorithmic bytes per launch against 8 TB/s) beside it; traffic
                   (measured HBM bytes per launch) from the committed rocprofv3 counter summary
-                  when it was taken on the current kernel source, else null;
+                  when it was taken on the current kernel source, else null; each fraction is
+                  also quoted against the chip's own peak (measured_peaks: HBM copy, FP32 and
+                  FP64 FMA and v_rsq_f32 lane rates, bf16 and FP32 MFMA, from
+                  pecnn_measure_peaks);
   cpu_baseline  - the FP64 oracle's CNN frame on a bounded sample, single thread;
   config        - the workload, raw frame rate, mass-spring rate, RMS and fallbacks, and an
                   untimed accuracy leg: RMS after --acc-frames network frames (default 100, the
@@ -471,11 +474,23 @@ def main():
 
     kname = ("ms_step_kernel (pair-cell frame, cfg %d)" % ms_cfg if pair else
              "cnn_fwd_bf16_kernel<32, %s>" % CNN_TILES.get(cnn_cfg, "?"))
+    # the chip's own peaks, measured with short synthetic kernels (untimed; 2 GiB scratch so that
+    # the copy streams from HBM rather than the last-level cache)
+    scratch = torch.empty((2 << 30) + (4 << 20), dtype=torch.uint8, device=dev)
+    pk = L.pecnn_measure_peaks(scratch, stream=st)
+    del scratch
+    measured = {"hbm_copy_GB_per_s": pk["hbm_copy_bytes_per_s"] / 1e9,
+                "fp32_valu_Tops": pk["fp32_valu_fma_lane_ops_per_s"] / 1e12,
+                "rsq_f32_Tops": pk["rsq_f32_lane_ops_per_s"] / 1e12,
+                "fp64_valu_Tops": pk["fp64_valu_fma_lane_ops_per_s"] / 1e12,
+                "bf16_mfma_TFLOPs": pk["bf16_mfma_flop_per_s"] / 1e12,
+                "fp32_mfma_TFLOPs": pk["fp32_mfma_flop_per_s"] / 1e12}
     hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
-           "algorithmic_bytes_per_launch": alg_bytes}
+           "algorithmic_bytes_per_launch": alg_bytes,
+           "measured_peak": measured["hbm_copy_GB_per_s"], "frac_of_measured": achieved / measured["hbm_copy_GB_per_s"]}
     if pair:
-        roof = hbm
+        roof = dict(hbm)
     else:
         # the frame's elementwise arithmetic takes longer than its HBM traffic at the peaks
         # (alu_ops_per_node / 16 lanes per SIMD cycle against 73 B / 8 TB/s), so the ALU roofline binds
@@ -485,8 +500,11 @@ def main():
                 "frac": a_tops / ALU_PEAK_TOPS, "traffic": traffic, "kernel": kname,
                 "algorithmic_ops_per_launch": ops, "ops_per_node": alu_ops_per_node(ch),
                 "floor_ms": 1e3 * ops / (ALU_PEAK_TOPS * 1e12),
-                "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac", "algorithmic_bytes_per_launch")},
+                "measured_peak": measured["fp32_valu_Tops"], "frac_of_measured": a_tops / measured["fp32_valu_Tops"],
+                "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac", "algorithmic_bytes_per_launch",
+                                            "measured_peak", "frac_of_measured")},
                 "hbm_floor_ms": 1e3 * alg_bytes / (HBM_PEAK_GBS * 1e9)}
+    roof["measured_peaks"] = measured
 
     raw = N * args.steps / t_roll
     value = raw * stride

@@ -300,6 +300,19 @@ int pecnn_autotune(pecnn_plan* plan, const cloth_ms_params* p, const pecnn_model
                    float* s_a, float* s_b, float* s_c, int32_t reps, float* ms_ms, float* cnn_ms,
                    void* stream);
 
+/* ------------------------------------------------------------------ measured peaks */
+
+/* Peaks of the current device measured with short synthetic kernels, for quoting the rooflines
+   against the chip at hand as well as its datasheet (not a step of the method). out: host
+   double [6]: [0] HBM copy bandwidth, bytes read plus written per second; [1] FP32 VALU FMA
+   lane operations per second; [2] v_rsq_f32 lane operations per second; [3] FP64 VALU FMA lane
+   operations per second; [4] bf16 MFMA (16x16x32) FLOP per second; [5] FP32 MFMA (16x16x4)
+   FLOP per second. scratch: caller-owned device buffer, 256-byte aligned, of at least 64 MiB;
+   the copy moves half of what is left after 2 MiB of kernel results into the other half, so a
+   buffer of 2 GiB or more measures HBM rather than the 256 MB last-level cache. Its contents
+   are overwritten. Synchronous on 'stream' (about 15 ms). */
+int pecnn_measure_peaks(double* out, void* scratch, size_t scratch_bytes, void* stream);
+
 const char* pecnn_status_string(int status);
 const char* pecnn_last_error(void);
 /* Library version, incremented when the ABI changes. */

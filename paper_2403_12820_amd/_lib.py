@@ -80,6 +80,7 @@ def lib():
         "pecnn_gather_windows": ([vp, i64, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp], i32),
         "pecnn_workspace_bytes": ([vp, P(Model), i32, P(sz)], i32),
         "pecnn_autotune": ([vp, P(MsParams), P(Model), vp, vp, vp, i32, vp, vp, vp], i32),
+        "pecnn_measure_peaks": ([vp, vp, sz, vp], i32),
         "pecnn_status_string": ([i32], C.c_char_p),
         "pecnn_last_error": ([], C.c_char_p),
         "pecnn_version": ([], i32),
@@ -100,6 +101,7 @@ def exported_symbols():
             "pecnn_forward", "pecnn_backward", "pecnn_rollout", "cloth_reduce_fp64", "cloth_reduce_fp64_noalloc",
             "pecnn_loss_mse",
             "pecnn_adam_step", "pecnn_gather_windows", "pecnn_workspace_bytes", "pecnn_autotune",
+            "pecnn_measure_peaks",
             "pecnn_status_string", "pecnn_last_error", "pecnn_version"]
 
 
@@ -296,3 +298,15 @@ def pecnn_autotune(plan: Plan, params: MsParams, model, s_a, s_b, s_c, reps=10, 
     check(lib().pecnn_autotune(plan.handle, C.byref(params), C.byref(model) if model is not None else None,
                                _ptr(s_a), _ptr(s_b), _ptr(s_c), int(reps), ms, cn, _stream(stream)), "pecnn_autotune")
     return list(ms), list(cn)
+
+
+PEAK_KEYS = ("hbm_copy_bytes_per_s", "fp32_valu_fma_lane_ops_per_s", "rsq_f32_lane_ops_per_s",
+             "fp64_valu_fma_lane_ops_per_s", "bf16_mfma_flop_per_s", "fp32_mfma_flop_per_s")
+
+
+def pecnn_measure_peaks(scratch, stream=None):
+    """The device's measured peaks (pecnn_measure_peaks) as a dict keyed by PEAK_KEYS."""
+    out = (C.c_double * 6)()
+    check(lib().pecnn_measure_peaks(out, _ptr(scratch), scratch.numel() * scratch.element_size(), _stream(stream)),
+          "pecnn_measure_peaks")
+    return dict(zip(PEAK_KEYS, list(out)))
