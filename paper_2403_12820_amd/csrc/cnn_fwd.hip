@@ -59,17 +59,32 @@ __global__ __launch_bounds__(256) void cnn_fwd_kernel(
     const int r0 = (lt / tiles_x) * TY, c0 = (lt % tiles_x) * TX;
 
     // Stage S^k and S^k - S^{k-1} over the tile plus a one-node halo, clamped to the grid
-    // (the clamp-to-edge padding of the convolution).
-    for (int e = threadIdx.x; e < 6 * PL; e += 256) {
-      const int c = e / PL;
-      const int rem = e - c * PL;
-      const int rr = rem / HX, cc = rem - (rem / HX) * HX;
-      const int gi = min(max(r0 + rr - 1, 0), I.H - 1);
-      const int gj = min(max(c0 + cc - 1, 0), I.W - 1);
-      const int64_t q = (int64_t)c * N + I.off + (int64_t)gi * I.W + gj;
-      const float sk = s_cur[q];
-      tS[e] = sk;
-      tD[e] = sk - s_prev[q];
+    // (the clamp-to-edge padding of the convolution); every load of a thread is issued before
+    // its first store.
+    constexpr int NST = (6 * PL + 255) / 256;
+    float vs[NST], vp[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      vs[k] = vp[k] = 0.f;
+      if (e < 6 * PL) {
+        const int c = e / PL;
+        const int rem = e - c * PL;
+        const int rr = rem / HX, cc = rem - (rem / HX) * HX;
+        const int gi = min(max(r0 + rr - 1, 0), I.H - 1);
+        const int gj = min(max(c0 + cc - 1, 0), I.W - 1);
+        const int64_t q = (int64_t)c * N + I.off + (int64_t)gi * I.W + gj;
+        vs[k] = s_cur[q];
+        vp[k] = s_prev[q];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      if (e < 6 * PL) {
+        tS[e] = vs[k];
+        tD[e] = vs[k] - vp[k];
+      }
     }
     __syncthreads();
 
