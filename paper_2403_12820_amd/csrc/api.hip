@@ -10,6 +10,8 @@
 #include <functional>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.hpp"
 
 namespace pecnn {
@@ -67,6 +69,15 @@ static bool finite_pos(float x) { return isfinite(x) && x > 0.f; }
 static bool finite_nonneg(float x) { return isfinite(x) && x >= 0.f; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// A roctx range over a host-side scope (a no-op unless a tracer such as rocprofv3
+// --marker-trace is attached): the entry points that queue many kernels mark their phases.
+struct TraceRange {
+  explicit TraceRange(const char* what) { roctxRangePushA(what); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 static int check_ms_params(const cloth_ms_params* p) {
   if (!p) { set_error("null cloth_ms_params"); return PECNN_E_INVALID; }
@@ -591,6 +602,7 @@ int pecnn_forward(const pecnn_plan* p, const pecnn_model* m, const float* s_prev
 int pecnn_backward(const pecnn_plan* p, const pecnn_model* m, const float* s_prev, const float* s_cur,
                    const float* g_next, float* g_cur, float* g_prev, float* g_theta, void* ws, size_t ws_bytes,
                    void* stream) {
+  TraceRange tr("pecnn_backward");
   int rc = check_plan(p);
   if (rc) return rc;
   if ((rc = check_model(m))) return rc;
@@ -775,6 +787,7 @@ static int repair_chunk(pecnn_plan* p, const MsParamsDev& sim, const pecnn_guard
 int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* simp, const pecnn_guard* g,
                   float* s_prev, float* s_cur, int32_t n_steps, int32_t* fallback, double* stats, void* ws,
                   size_t ws_bytes, void* stream) {
+  TraceRange tr("pecnn_rollout");
   int rc = check_plan(p);
   if (rc) return rc;
   if ((rc = check_model(m))) return rc;
@@ -810,6 +823,7 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
 
   // prologue: energy scale, starting diagnostics, fall-back mask
   {
+    TraceRange tp("pecnn_rollout prologue");
     std::vector<double> eref(p->n), escale(p->n);
     const double gn = sqrt((double)simp->g[0] * simp->g[0] + (double)simp->g[1] * simp->g[1] + (double)simp->g[2] * simp->g[2]);
     for (int b = 0; b < p->n; ++b) {
@@ -884,7 +898,10 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
       }
       gc->entries.push_back(GraphEntry{key, exec});
     }
-    PECNN_HIP(hipGraphLaunch(exec, st));
+    {
+      TraceRange tc(with_ms ? "pecnn_rollout chunk (with mass-spring steps)" : "pecnn_rollout chunk");
+      PECNN_HIP(hipGraphLaunch(exec, st));
+    }
     const int k0 = k, pi0 = pi, ci0 = ci;
     for (int i = 0; i < len; ++i) {
       const int di = rollout_dest(k + i, prefix, pi, ci);
@@ -902,6 +919,7 @@ int pecnn_rollout(pecnn_plan* p, const pecnn_model* m, const cloth_ms_params* si
       PECNN_HIP(hipEventSynchronize(gc->count_ready[pending]));
       const bool fallen = gc->host_count[pending] > 0;
       if (fallen && !with_ms) {
+        TraceRange trp("pecnn_rollout repair");
         rc = repair_chunk(p, sim, g, B, pi0, ci0, k0, prefix, w.T, len, guard_on, fallback, stats_d, w, st);
         if (rc) return rc;
       }
@@ -975,6 +993,7 @@ static int autotune_impl(pecnn_plan* p, const cloth_ms_params* prm, const pecnn_
 
 int pecnn_autotune(pecnn_plan* p, const cloth_ms_params* prm, const pecnn_model* m, float* s_a, float* s_b,
                    float* s_c, int32_t reps, float* ms_ms, float* cnn_ms, void* stream) {
+  TraceRange tr("pecnn_autotune");
   int rc = check_plan(p);
   if (rc) return rc;
   if ((rc = check_ms_params(prm))) return rc;

@@ -467,6 +467,23 @@ def test_rollout_partial_trip_at_a_later_check(torch_mod, L, n):
         assert np.array_equal(got_p[:, sl], prev.cpu().numpy()[:, sl])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rollout_guard_catches_nan_weights(torch_mod, L, prec):
+    """A network with NaN parameters gives NaN frames: the first check sends every instance to the
+    simulator (a NaN stretch or energy gain fails every bound), and the call returns normally."""
+    torch = torch_mod
+    n, every, sub = 6, 3, 4
+    batch, plan, model, s0, s1 = _rollout_setup(L, torch, [(24, 40), (9, 9)], 1500, prec=prec)
+    model._theta_ref.fill_(float("nan"))
+    a, b = dev_tensor(s0), dev_tensor(s1)
+    fb = torch.zeros(batch.n, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(4 * batch.n, dtype=torch.float64, device="cuda")
+    L.pecnn_rollout(plan, model, L.ms_params(MAT), _guard(L, every=every, sub=sub), a, b, n, fb, stats)
+    torch.cuda.synchronize()
+    assert np.all(fb.cpu().numpy() == 1)
+    assert np.all(stats.cpu().numpy().reshape(-1, 4)[:, 3] == every)
+
+
 def test_rollout_preset_fallback_instance(torch_mod, L):
     """A caller-preset flag sends that instance to the mass-spring step from the first frame while
     the others keep the network."""

@@ -58,6 +58,7 @@ def test_host_runtime_under_address_sanitizer(tmp_path):
         assert p.returncode == 0, (s, out[-2000:])
     lib = str(tmp_path / "libpecnn.so")
     subprocess.check_call([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
-                           "-o", lib, *[str(tmp_path / (os.path.basename(s) + ".o")) for s in srcs]])
+                           "-o", lib, *[str(tmp_path / (os.path.basename(s) + ".o")) for s in srcs],
+                           "-lrocprofiler-sdk-roctx"])
     out = _run_pytest([os.path.join("tests", "test_abi.py")], {"LD_PRELOAD": rts[-1], "PECNN_LIB": lib})
     assert "passed" in out
