@@ -1,5 +1,5 @@
 // Reverse mode of the CNN frame (section 3.2.1: the parameters w, b are optimised by gradient
-// backpropagation through eqs. 5-7), FP32, deterministic. Three kernels:
+// backpropagation through eqs. 5-7), FP32, deterministic. Three steps in two launches:
 //
 //  1. bwd_tile (cnn_bwd_tile.hip): on the matrix cores, per tile of 64 x 4 nodes: recomputes the
 //     cell, pulls the adjoint of eq. (5) back through the heads, the ISRU branches and the two
@@ -8,7 +8,7 @@
 //  2. bwd_gather: one thread per node: the adjoint of the clamped im2col, written as a gather
 //     over the (neighbour, tap) pairs that read this node, plus the direct terms of eq. (5).
 //     Accumulates into g_cur and g_prev.
-//  3. wgrad_final: a fixed-order sum of the partial rows into g_theta.
+//  3. wgrad_final: a fixed-order sum of the partial rows into g_theta, in the same launch as 2.
 // The pair cell (section 3.2 read literally) and the sphere's reverse mode follow below.
 #include "cnn_bwd_table.hpp"
 #include "cnn_common.hpp"
@@ -33,13 +33,13 @@ __device__ __forceinline__ bool chunk_node(const InstDev* inst, const int32_t* p
 // For node q: g_cur/g_prev += direct terms of eq. (5) + adjoint of the clamped, centre-differenced
 // im2col: a tap (c, o) of node p read S_c(clamp(p + o)) (and, for positions, -S_c(p)); plus, with a
 // pressure, the adjoint of the eq. (3) term of q and of its four neighbours, which read x_q.
-__global__ __launch_bounds__(256) void bwd_gather_kernel(
-    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+__device__ __forceinline__ void bwd_gather_chunk(
+    int t, const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_cur, const float* __restrict__ g_next, int64_t N,
     float dt, const float* __restrict__ tab, float* __restrict__ g_cur, float* __restrict__ g_prev) {
   int b;
   int local;
-  if (!chunk_node(inst, prefix, chunk_inst, blockIdx.x, b, local)) return;
+  if (!chunk_node(inst, prefix, chunk_inst, t, b, local)) return;
   const InstDev I = inst[b];
   const int qi = local / I.W, qj = local - (local / I.W) * I.W;
   const int64_t q = I.off + local;
@@ -98,26 +98,50 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(
     for (int c = 0; c < 6; ++c) g_prev[c * N + q] += accP[c];
 }
 
-// g_theta[e] += sum over the partial rows: 32 threads per parameter each sum a fixed stride of
-// rows, then a fixed-order combine in LDS (deterministic). 32 parameters per workgroup, so that a
-// batch of 4,067 parameters spreads over 128 workgroups.
-constexpr int kWfParams = 32, kWfGroups = 32;
-__global__ __launch_bounds__(kWfParams * kWfGroups) void wgrad_final_kernel(const float* __restrict__ partial,
-                                                                            int n_rows, int P,
-                                                                            float* __restrict__ g_theta) {
+// g_theta[e] += sum over the partial rows, one block of 256 threads for kWfParams parameters: each
+// of kWfGroups threads per parameter sums a fixed stride of rows, then a fixed-order combine in LDS
+// (deterministic). The loads of eight rows are issued before their adds.
+constexpr int kWfParams = 32, kWfGroups = 8;
+static_assert(kWfParams * kWfGroups == 256, "one 256-thread block per parameter group");
+__device__ __forceinline__ void wgrad_final_block(int blk, const float* __restrict__ partial, int n_rows, int P,
+                                                  float* __restrict__ g_theta) {
   __shared__ double sh[kWfGroups][kWfParams + 1];
   const int pl = threadIdx.x % kWfParams, r0 = threadIdx.x / kWfParams;
-  const int e = blockIdx.x * kWfParams + pl;
+  const int e = blk * kWfParams + pl;
   double s = 0.0;
-  if (e < P)
+  if (e < P) {
+#pragma unroll 8
     for (int r = r0; r < n_rows; r += kWfGroups) s += (double)partial[(int64_t)r * P + e];
+  }
   sh[r0][pl] = s;
   __syncthreads();
   if (r0 == 0 && e < P) {
-    double t = 0.0;
-    for (int k = 0; k < kWfGroups; ++k) t += sh[k][pl];
-    g_theta[e] += (float)t;
+    double u = 0.0;
+#pragma unroll
+    for (int k = 0; k < kWfGroups; ++k) u += sh[k][pl];
+    g_theta[e] += (float)u;
   }
+}
+
+__host__ __device__ inline int wgrad_final_blocks(int P) { return (P + kWfParams - 1) / kWfParams; }
+
+__global__ __launch_bounds__(256) void wgrad_final_kernel(const float* __restrict__ partial, int n_rows, int P,
+                                                          float* __restrict__ g_theta) {
+  wgrad_final_block(blockIdx.x, partial, n_rows, P, g_theta);
+}
+
+// The gather and the parameter sum read disjoint outputs of bwd_tile and write disjoint arrays, so
+// one launch runs both: the first nw blocks sum parameters (dispatched first, they overlap the
+// gather), the rest gather one chunk each.
+__global__ __launch_bounds__(256) void bwd_gather_final_kernel(
+    int nw, const float* __restrict__ partial, int n_rows, int P, float* __restrict__ g_theta,
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+    const uint8_t* __restrict__ pin, const float* __restrict__ s_cur, const float* __restrict__ g_next, int64_t N,
+    float dt, const float* __restrict__ tab, float* __restrict__ g_cur, float* __restrict__ g_prev) {
+  if ((int)blockIdx.x < nw)
+    wgrad_final_block(blockIdx.x, partial, n_rows, P, g_theta);
+  else
+    bwd_gather_chunk((int)blockIdx.x - nw, inst, prefix, chunk_inst, pin, s_cur, g_next, N, dt, tab, g_cur, g_prev);
 }
 
 // ---------------------------------------------------------------- the pair cell
@@ -276,8 +300,7 @@ int pair_backward_launch(const pecnn_plan* plan, const pecnn_model* m, const flo
   hipLaunchKernelGGL(pair_wgrad_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, sc,
                      gn, plan->total, m->theta, m->isru_alpha, m->dt, partial);
   PECNN_LAUNCH_CHECK("pair_wgrad_kernel");
-  hipLaunchKernelGGL(wgrad_final_kernel, dim3((kPairP + kWfParams - 1) / kWfParams), dim3(kWfParams * kWfGroups), 0,
-                     st, partial, nt, kPairP, gth);
+  hipLaunchKernelGGL(wgrad_final_kernel, dim3(wgrad_final_blocks(kPairP)), dim3(256), 0, st, partial, nt, kPairP, gth);
   PECNN_LAUNCH_CHECK("wgrad_final_kernel");
   return PECNN_OK;
 }
@@ -383,15 +406,15 @@ int backward_launch(const pecnn_plan* plan, const pecnn_model* m, const float* s
   const int P = (int)theta_count(m->ch);
   int rc = bwd_tile_launch(plan, m, sp, sc, gn, tab, partial, st);
   if (rc) return rc;
+  const int nrows = bwd_tile_grid(plan), nw = wgrad_final_blocks(P);
   if (gc || gp) {
-    hipLaunchKernelGGL(bwd_gather_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, pre, plan->d_chunk_inst, plan->pin, sc,
-                       gn, plan->total, m->dt, tab, gc, gp);
-    PECNN_LAUNCH_CHECK("bwd_gather_kernel");
+    hipLaunchKernelGGL(bwd_gather_final_kernel, dim3(nw + nt), dim3(256), 0, st, nw, partial, nrows, P, gth, plan->d_inst,
+                       pre, plan->d_chunk_inst, plan->pin, sc, gn, plan->total, m->dt, tab, gc, gp);
+    PECNN_LAUNCH_CHECK("bwd_gather_final_kernel");
+  } else {
+    hipLaunchKernelGGL(wgrad_final_kernel, dim3(nw), dim3(256), 0, st, partial, nrows, P, gth);
+    PECNN_LAUNCH_CHECK("wgrad_final_kernel");
   }
-  const int nrows = bwd_tile_grid(plan);
-  hipLaunchKernelGGL(wgrad_final_kernel, dim3((P + kWfParams - 1) / kWfParams), dim3(kWfParams * kWfGroups), 0, st,
-                     partial, nrows, P, gth);
-  PECNN_LAUNCH_CHECK("wgrad_final_kernel");
   return PECNN_OK;
 }
 
