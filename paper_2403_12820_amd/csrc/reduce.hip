@@ -46,8 +46,28 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Square root of d2 = |x_i - x_j|^2 for FP32 positions widened to FP64: d2 is 0 or at least
+// 2^-298 (the square of the smallest FP32 step), so no rescaling of tiny arguments is needed.
+// v_rsq_f64 gives the seed y ~ d2^-1/2; one coupled Newton step refines g ~ sqrt(d2) and
+// h ~ 1/(2 sqrt(d2)) together, and two Newton corrections g += (d2 - g^2) h finish g (Markstein's
+// iteration for the square root). d2 = 0 gives 0; a NaN stays NaN.
+__device__ __forceinline__ double spring_length(double d2) {
+  const double y = __builtin_amdgcn_rsq(d2);
+  double g = d2 * y, h = 0.5 * y;
+  const double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double e = __builtin_fma(-g, g, d2);
+  g = __builtin_fma(e, h, g);
+  e = __builtin_fma(-g, g, d2);
+  g = __builtin_fma(e, h, g);
+  return d2 == 0.0 ? 0.0 : g;
+}
+
 // One wave per chunk of kChunk nodes: lane k takes nodes k, k + 64, k + 128, k + 192 of the
-// chunk in that order (every load stays coalesced), then the wave sums its lanes.
+// chunk in that order (every load stays coalesced), then the wave sums its lanes. The stretch
+// ratios keep the longest spring of each family and scale it once at the end: a product with a
+// positive constant is monotone in its other factor, so max(r) / L = max(r / L) exactly.
 constexpr int kLaneNodes = kChunk / 64;
 static_assert(kChunk % 64 == 0, "a chunk is whole waves of nodes");
 
@@ -64,44 +84,53 @@ __global__ __launch_bounds__(64) void reduce_chunk_kernel(
   // row and column of the lane's first node; each further node is 64 along the row-major order
   int i = first / I.W, j = first - (first / I.W) * I.W;
   const int di = 64 / I.W, dj = 64 - (64 / I.W) * I.W;
-  const double m = I.mass;
-  const double ge[3] = {(double)P.g[0] + I.ax, (double)P.g[1] + I.ay, (double)P.g[2] + I.az};
+  const double hm = 0.5 * (double)I.mass;
+  const double mg[3] = {(double)I.mass * ((double)P.g[0] + I.ax), (double)I.mass * ((double)P.g[1] + I.ay),
+                        (double)I.mass * ((double)P.g[2] + I.az)};
   const double h = I.h;
   const double L[3] = {h, 1.4142135623730951 * h, 2.0 * h};
-  const double ih = 1.0 / h;  // one division per lane; the stretch ratios multiply
-  const double iL[3] = {ih, 0.70710678118654752 * ih, 0.5 * ih};
-  double e2 = 0.0, en = 0.0, st_s = 0.0, st_a = 0.0;
+  const double hk[3] = {0.5 * (double)P.k[0], 0.5 * (double)P.k[1], 0.5 * (double)P.k[2]};
+  double e2 = 0.0, en = 0.0, rmax[3] = {0.0, 0.0, 0.0};
   for (int q = 0; q < kLaneNodes; ++q) {
     const int local = first + 64 * q;
     if (local >= n_nodes) break;
     const int p = (int)I.off + local;
-    double x[3];
+    double x[3], v[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       x[a] = gld(s, (unsigned)(a * N32 + p));
-      const double v = gld(s, (unsigned)((3 + a) * N32 + p));
-      en += 0.5 * m * v * v - m * ge[a] * x[a];
-      if (s_ref) {
+      v[a] = gld(s, (unsigned)((3 + a) * N32 + p));
+    }
+    // kinetic energy minus the work of gravity and the external field
+    const double vv = __builtin_fma(v[2], v[2], __builtin_fma(v[1], v[1], v[0] * v[0]));
+    const double gx = __builtin_fma(mg[2], x[2], __builtin_fma(mg[1], x[1], mg[0] * x[0]));
+    en += __builtin_fma(hm, vv, -gx);
+    if (s_ref) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
         const double d = x[a] - (double)gld(s_ref, (unsigned)(a * N32 + p));
-        e2 += d * d;
+        e2 = __builtin_fma(d, d, e2);
       }
     }
+    // the forward half of the 12 springs, so that each is counted once; which of them exist
+    // follows from five comparisons of the node's row and column with the grid's edges
+    const bool r1 = i + 1 < I.H, r2 = i + 2 < I.H, c1 = j + 1 < I.W, c2 = j + 2 < I.W, cm = j >= 1;
+    const bool ok[6] = {c1, r1, r1 && c1, r1 && cm, c2, r2};
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const int ii = i + kHalf[k].dy, jj = j + kHalf[k].dx;
-      // structural springs pointing backwards are visited by the other end; stretch needs all
-      if (ii < 0 || ii >= I.H || jj < 0 || jj >= I.W) continue;
+      if (!ok[k]) continue;
       const int pj = p + kHalf[k].dy * I.W + kHalf[k].dx;
       double d2 = 0.0;
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double d = x[a] - (double)gld(s, (unsigned)(a * N32 + pj));
-        d2 += d * d;
+        d2 = __builtin_fma(d, d, d2);
       }
-      const double r = sqrt(d2);
+      const double r = spring_length(d2);
       const int f = kHalf[k].fam;
       const double dr = r - L[f];
-      en += 0.5 * (double)P.k[f] * dr * dr;
-      const double ratio = r * iL[f];
-      if (f == 0) st_s = fmax(st_s, ratio);
-      st_a = fmax(st_a, ratio);
+      en = __builtin_fma(hk[f] * dr, dr, en);
+      rmax[f] = fmax(rmax[f], r);
     }
     i += di;
     j += dj;
@@ -110,10 +139,14 @@ __global__ __launch_bounds__(64) void reduce_chunk_kernel(
       ++i;
     }
   }
+  // stretch ratios r / L with 1 / L = 1 / h, 1 / (sqrt 2 h), 1 / (2 h)
+  const double ih = 1.0 / h;
+  const double rs = rmax[0] * ih;
+  const double ra = fmax(rs, fmax(rmax[1] * (0.70710678118654752 * ih), rmax[2] * (0.5 * ih)));
   e2 = wave_sum(e2);
   en = wave_sum(en);
-  st_s = wave_max(st_s);
-  st_a = wave_max(st_a);
+  const double st_s = wave_max(rs);
+  const double st_a = wave_max(ra);
   if (threadIdx.x == 0) {
     partial[4 * t + 0] = e2;
     partial[4 * t + 1] = en;
