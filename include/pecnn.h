@@ -259,8 +259,9 @@ int cloth_reduce_fp64_noalloc(const pecnn_plan* plan, const cloth_ms_params* p, 
 
 /* Data term of eq. (8) for one predicted state: w / n_free * sum over unpinned nodes of
    |x_hat - x|^2 / sx^2 + |v_hat - v|^2 / sv^2. Adds the value to *loss (device double, one
-   value) and its gradient w.r.t. s_hat to g_hat (device [6][N_total], +=, may be NULL).
-   n_free = number of unpinned nodes over which the mean is taken (> 0).
+   value) and its gradient w.r.t. s_hat to g_hat (device [6][N_total], +=). Either may be NULL,
+   not both: with loss NULL only the gradient is formed (the same bits, no sums; one launch
+   instead of two). n_free = number of unpinned nodes over which the mean is taken (> 0).
    ws: pecnn_workspace_bytes(plan, NULL, PECNN_WS_REDUCE). */
 int pecnn_loss_mse(const pecnn_plan* plan, const float* s_hat, const float* s_true, float sx,
                    float sv, float w, int64_t n_free, double* loss, float* g_hat, void* ws,

@@ -667,7 +667,10 @@ int pecnn_loss_mse(const pecnn_plan* p, const float* s_hat, const float* s_true,
                    int64_t n_free, double* loss, float* g_hat, void* ws, size_t ws_bytes, void* stream) {
   int rc = check_plan(p);
   if (rc) return rc;
-  if (!s_hat || !s_true || !loss) { set_error("null state or loss"); return PECNN_E_INVALID; }
+  if (!s_hat || !s_true || (!loss && !g_hat)) {
+    set_error("null state, or neither loss nor gradient");
+    return PECNN_E_INVALID;
+  }
   if (!finite_pos(sx) || !finite_pos(sv) || !isfinite(w) || n_free < 1) {
     set_error("scales must be finite and > 0, weight finite, n_free >= 1");
     return PECNN_E_INVALID;

@@ -266,12 +266,39 @@ __global__ __launch_bounds__(256) void loss_final_kernel(const double* __restric
   if (threadIdx.x == 0) *loss += scale * s;
 }
 
+// The gradient alone (no value asked for): the same per-element expression as loss_chunk_kernel,
+// so g is the same to the bit, without the sums.
+__global__ __launch_bounds__(256) void loss_grad_kernel(
+    const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, const int32_t* __restrict__ chunk_inst,
+    int64_t N, const uint8_t* __restrict__ pin, const float* __restrict__ sh_, const float* __restrict__ st_, float isx2,
+    float isv2, float gscale, float* __restrict__ g) {
+  const int t = blockIdx.x;
+  const int b = chunk_inst[t];
+  const InstDev I = inst[b];
+  const int local = (t - prefix[b]) * kChunk + (int)threadIdx.x;
+  if (local >= I.H * I.W) return;
+  const int64_t p = I.off + local;
+  if (pin[p]) return;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const float d = sh_[c * N + p] - st_[c * N + p];
+    const float is2 = c < 3 ? isx2 : isv2;
+    g[c * N + p] += gscale * d * is2;
+  }
+}
+
 int loss_launch(const pecnn_plan* plan, const float* s_hat, const float* s_true, float sx, float sv, float w,
                 int64_t n_free, double* loss, float* g, void* ws, hipStream_t st) {
   const int nt = plan->n_tiles[kCfgChunk];
   double* partial = (double*)ws;
   const float isx2 = 1.f / (sx * sx), isv2 = 1.f / (sv * sv);
   const float gscale = (float)(2.0 * (double)w / (double)n_free);
+  if (!loss) {
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk],
+                       plan->d_chunk_inst, plan->total, plan->pin, s_hat, s_true, isx2, isv2, gscale, g);
+    PECNN_LAUNCH_CHECK("loss_grad_kernel");
+    return PECNN_OK;
+  }
   hipLaunchKernelGGL(loss_chunk_kernel, dim3(nt), dim3(256), 0, st, plan->d_inst, plan->d_prefix[kCfgChunk],
                      plan->d_chunk_inst, plan->total, plan->pin, s_hat, s_true, isx2, isv2, gscale, partial, g);
   PECNN_LAUNCH_CHECK("loss_chunk_kernel");

@@ -164,9 +164,11 @@ class Trainer:
             self.phys = torch.empty(U, 6, N, device=self.device)
             self.ws_m = plan.workspace(L.WS_MS_STEP)
 
-    def gradient(self, buf, plan, n_free, sx, sv, one_step_weight=1.0, alpha=0.0, sim=None, stride=10):
+    def gradient(self, buf, plan, n_free, sx, sv, one_step_weight=1.0, alpha=0.0, sim=None, stride=10,
+                 with_loss=True):
         """Loss and theta gradient (self.loss, self.g) of the unrolled prediction from buf[0], buf[1]
-        (S^{k-1}, S^k) against buf[2:] (the next saved frames), by BPTT."""
+        (S^{k-1}, S^k) against buf[2:] (the next saved frames), by BPTT. With with_loss False only
+        the gradient is formed (the same bits) and self.loss is left as it was."""
         from . import _lib as L
         if not 0.0 <= alpha <= 1.0 or (alpha > 0.0 and sim is None):
             raise ValueError("alpha must lie in [0, 1]; the physics term needs the simulator parameters")
@@ -180,17 +182,19 @@ class Trainer:
                 # physics target of eq. (8): the simulator's frame from this frame's input state
                 L.cloth_ms_step(plan, sim, S[-1], self.phys[t], stride, ws=self.ws_m)
             S.append(pred[t])
-        self.loss.zero_()
+        loss = self.loss if with_loss else None
+        if with_loss:
+            self.loss.zero_()
         grads.zero_()
         for t in range(U):
             # l_8: mean over the unrolled frames; l_1: the first frame once more
             w = 1.0 / U + (one_step_weight if t == 0 else 0.0)
             if alpha < 1.0:
-                L.pecnn_loss_mse(plan, pred[t], buf[t + 2], sx, sv, (1.0 - alpha) * w, n_free, self.loss, grads[t],
+                L.pecnn_loss_mse(plan, pred[t], buf[t + 2], sx, sv, (1.0 - alpha) * w, n_free, loss, grads[t],
                                  ws=self.ws_r)
             if alpha > 0.0:
                 # impulses only: the position planes get a vanishing weight
-                L.pecnn_loss_mse(plan, pred[t], self.phys[t], NO_POSITIONS, sv, alpha * w, n_free, self.loss,
+                L.pecnn_loss_mse(plan, pred[t], self.phys[t], NO_POSITIONS, sv, alpha * w, n_free, loss,
                                  grads[t], ws=self.ws_r)
         self.g.zero_()
         for t in range(U - 1, -1, -1):
@@ -228,10 +232,11 @@ class Trainer:
         return extra
 
     def step(self, wb: WindowBatch, plan, n_free, sx, sv, one_step_weight=1.0, lr=None, alpha=0.0, sim=None,
-             stride=10):
-        """One iteration: unrolled forward, loss, BPTT, Adam. Returns the loss (device scalar)."""
+             stride=10, with_loss=True):
+        """One iteration: unrolled forward, loss, BPTT, Adam. Returns the loss (device scalar; its
+        value is this iteration's only with with_loss)."""
         from . import _lib as L
-        self.gradient(wb.buf, plan, n_free, sx, sv, one_step_weight, alpha, sim, stride)
+        self.gradient(wb.buf, plan, n_free, sx, sv, one_step_weight, alpha, sim, stride, with_loss)
         self.t += 1
         L.pecnn_adam_step(self.theta, self.m, self.v, self.g, self.t, lr=self.lr if lr is None else lr)
         return self.loss
@@ -387,8 +392,11 @@ def train(n_scenes=64, size=64, n_val=8, iters=20000, n_win=32, n_unroll=8, ch=3
         c = classes[(it - 1) % len(classes)]
         plan, n_free = c.wb.sample(rng)
         lr_t = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (it - 1) / iters))
-        loss = tr.step(c.wb, plan, n_free, c.sx, c.sv, lr=lr_t, alpha=alpha, sim=c.traj.sim, stride=stride)
-        if it % log_every == 0 or it == 1 or it == iters:
+        log_it = it % log_every == 0 or it == 1 or it == iters
+        # the loss value is read on logged iterations only; the others form the gradient alone
+        loss = tr.step(c.wb, plan, n_free, c.sx, c.sv, lr=lr_t, alpha=alpha, sim=c.traj.sim, stride=stride,
+                       with_loss=log_it)
+        if log_it:
             lv = float(loss.item())
             vl = val_loss()
             curve.append((it, lv, vl))

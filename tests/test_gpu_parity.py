@@ -275,6 +275,11 @@ def test_backward_is_deterministic(torch_mod, L):
         torch.cuda.synchronize()
         res.append((gt.cpu().numpy(), gc.cpu().numpy()))
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    # without state gradients the parameter sum runs in a launch of its own: the same sum, bit for bit
+    gt = torch.zeros(th.size, device="cuda")
+    L.pecnn_backward(plan, model, a, b, g, None, None, gt)
+    torch.cuda.synchronize()
+    assert np.array_equal(gt.cpu().numpy(), res[0][0])
 
 
 def test_loss_and_adam_match_oracle(torch_mod, L):
@@ -291,6 +296,13 @@ def test_loss_and_adam_match_oracle(torch_mod, L):
     rv, rg = oracle.loss_mse(batch.pin, n_free, 0.01, 0.2, 0.75, sh, batch.state)
     assert abs(loss.item() - rv) <= 1e-6 * abs(rv)
     assert rel_inf(g.cpu().numpy(), rg) <= 1e-5
+    # the gradient alone (no value asked for): the same bits
+    g2 = torch.zeros(6, batch.total, device="cuda")
+    L.pecnn_loss_mse(plan, dev_tensor(sh), dev_tensor(batch.state), 0.01, 0.2, 0.75, n_free, None, g2)
+    torch.cuda.synchronize()
+    assert torch.equal(g, g2)
+    with pytest.raises(L.PecnnError):
+        L.pecnn_loss_mse(plan, dev_tensor(sh), dev_tensor(batch.state), 0.01, 0.2, 0.75, n_free, None, None)
     n = 4067
     th0 = I.random_array((n,), seed=702).astype(np.float32)
     gr = I.random_array((n,), seed=703).astype(np.float32)
