@@ -18,12 +18,32 @@ namespace pecnn {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
+// 16 bytes from a float address that is only 4-byte aligned: the copy states the true alignment,
+// and the target's code generator chooses the access (one 16-byte load on gfx950).
+__device__ __forceinline__ float4 gld4_dword(const float* __restrict__ base, unsigned idx) {
+  float4 v;
+  __builtin_memcpy(&v, reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(float), sizeof(float4));
+  return v;
+}
+
+// Element k of the result is element min(k + sh, 3) of p (sh >= 0).
+__device__ __forceinline__ float4 shift_clamped(float4 p, int sh) {
+  float4 r;
+  r.x = sh == 0 ? p.x : (sh == 1 ? p.y : (sh == 2 ? p.z : p.w));
+  r.y = sh == 0 ? p.y : (sh == 1 ? p.z : p.w);
+  r.z = sh == 0 ? p.z : p.w;
+  r.w = p.w;
+  return r;
+}
+
 // WPE: waves per SIMD the register allocation is held to (3 fits the tiles up to 256 nodes).
-// VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
-// so the halo rows load as 16-byte pieces; otherwise as single floats.
+// VEC: how the halo rows load. 1: every plane row starts 16-byte aligned (W and the instance
+// offsets are multiples of 4), so as aligned 16-byte pieces. 2: every instance is at least 4
+// wide, so as 16-byte pieces at 4-byte alignment, the piece that would cross the right edge of
+// the grid taken at W - 4 and its values moved into place in registers. 0: as single floats.
 // EXT: some instance of the batch has a pressure (eq. 3), added as a known external force, or a
 // sphere in the constraint of eq. (5); the others skip both uniformly.
-template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool EXT>
+template <int CH, int TX, int TY, bool A1, int WPE, int VEC, bool EXT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void cnn_fwd_bf16_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_prev, const float* __restrict__ s_cur,
@@ -131,11 +151,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         const int gi = min(max(r0 + it_rr[i] - 1, 0), I.H - 1);
         const int col = c0 + 4 * q;
         const unsigned rb = (unsigned)(c * N32 + off32 + gi * I.W);
-        if constexpr (VEC) {
+        if constexpr (VEC == 1) {
           // a piece right of the grid loads the last in-grid piece; staging keeps its last column
           const unsigned a = rb + (unsigned)min(col, I.W - 4);
           pS[i] = gld(reinterpret_cast<const float4*>(s_cur), a);
           pP[i] = gld(reinterpret_cast<const float4*>(s_prev), a);
+        } else if constexpr (VEC == 2) {
+          // the four columns from min(col, W - 4): inside the row for every W >= 4
+          const unsigned a = rb + (unsigned)min(col, I.W - 4);
+          pS[i] = gld4_dword(s_cur, a);
+          pP[i] = gld4_dword(s_prev, a);
         } else {
           const unsigned j0 = rb + min(col, I.W - 1), j1 = rb + min(col + 1, I.W - 1),
                          j2 = rb + min(col + 2, I.W - 1), j3 = rb + min(col + 3, I.W - 1);
@@ -168,8 +193,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
   };
 
-  // Registers -> LDS: FP32 S^k, FP32 position differences in time, bf16 velocity planes.
-  auto stage = [&]() {
+  // Registers -> LDS: FP32 S^k, FP32 position differences in time, bf16 velocity planes, for
+  // the tile whose first column is sc0 in an instance sW wide.
+  auto stage = [&](int sW, int sc0) {
 #pragma unroll
     for (int i = 0; i < NVT; ++i) {
       const int j = tid + 256 * i;
@@ -177,6 +203,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         const int row = j / QV, q = j - (j / QV) * QV;
         const int c = row / HY, rr = row - (row / HY) * HY;
         const int e = rr * RS + 4 + 4 * q;
+        if constexpr (VEC == 2) {
+          if (sc0 + TX > sW) {  // uniform: a tile crossing the right edge of the grid
+            // the piece holds columns b .. b + 3, b = min(col, W - 4); column col + k wants
+            // column min(col + k, W - 1), i.e. element min(k + sh, 3) with sh = col - b
+            const int col = sc0 + 4 * q, sh = col - min(col, sW - 4);
+            pS[i] = shift_clamped(pS[i], sh);
+            pP[i] = shift_clamped(pP[i], sh);
+          }
+        }
 
         *reinterpret_cast<float4*>(&tS[c * PLN + e]) = pS[i];
         const float4 d = make_float4(pS[i].x - pP[i].x, pS[i].y - pP[i].y, pS[i].z - pP[i].z, pS[i].w - pP[i].w);
@@ -227,9 +262,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const int rc0 = r0, cc0 = c0;
     // every prefetched register is consumed here on every path, so the next loads that reuse
     // them never wait on older stores
-    stage();
+    stage(Ic.W, cc0);
     __syncthreads();
-    if (VEC && cc0 + TX > Ic.W) {
+    if (VEC == 1 && cc0 + TX > Ic.W) {
       // a tile crossing the right edge of the grid: its 16-byte pieces right of the edge hold
       // the last in-grid piece, but the taps of the last column read the clamped copy of it
       // one column further; write that column (the only one off the grid that a node reads)
@@ -387,7 +422,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
   }
 }
 
-template <int CH, int TX, int TY, bool A1, int WPE, bool VEC, bool EXT>
+template <int CH, int TX, int TY, bool A1, int WPE, int VEC, bool EXT>
 static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const float* sc, float* sn,
                         const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
   const int n_tiles = plan->n_tiles[slot];
@@ -409,7 +444,7 @@ static void launch_bf16(const pecnn_plan* plan, int slot, const float* sp, const
                      skip, plan->d_sphere);
 }
 
-template <int CH, bool A1, bool VEC, bool EXT>
+template <int CH, bool A1, int VEC, bool EXT>
 static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                       const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
   const int slot = cnn_cfg_slot(cfg);
@@ -426,11 +461,16 @@ static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const fl
 template <int CH, bool A1>
 static int bf16_cfg(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                     const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
-  if (plan->has_pressure || plan->has_sphere)
-    return plan->vec4 ? bf16_cfg_v<CH, A1, true, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)
-                      : bf16_cfg_v<CH, A1, false, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
-  return plan->vec4 ? bf16_cfg_v<CH, A1, true, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st)
-                    : bf16_cfg_v<CH, A1, false, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+  int min_w = plan->W[0];
+  for (int b = 1; b < plan->n; ++b) min_w = min(min_w, plan->W[b]);
+  if (plan->has_pressure || plan->has_sphere) {
+    if (plan->vec4) return bf16_cfg_v<CH, A1, 1, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+    if (min_w >= 4) return bf16_cfg_v<CH, A1, 2, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+    return bf16_cfg_v<CH, A1, 0, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+  }
+  if (plan->vec4) return bf16_cfg_v<CH, A1, 1, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+  if (min_w >= 4) return bf16_cfg_v<CH, A1, 2, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
+  return bf16_cfg_v<CH, A1, 0, false>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
 }
 
 int cnn_forward_bf16_launch(const pecnn_plan* plan, int cfg, const pecnn_model* m, const float* sp,

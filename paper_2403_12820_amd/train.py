@@ -81,8 +81,9 @@ class WindowBatch:
         for b in self.scene_ids:
             assert traj.scenes[int(b)].H == self.H and traj.scenes[int(b)].W == self.W
         self.buf = torch.empty(n_unroll + 2, 6, n_win * self.npw, device=device)
-        self.inst = torch.empty(n_win, dtype=torch.int32, device=device)
-        self.frame = torch.empty(n_win, dtype=torch.int32, device=device)
+        # window instances and start frames, one device array so that one copy uploads both
+        self.idx = torch.empty(2, n_win, dtype=torch.int32, device=device)
+        self.inst, self.frame = self.idx[0], self.idx[1]
         self.device = device
         # Drawing a minibatch must not wait for the GPU to finish the previous iteration: the
         # pins of every scene stay on the device (a minibatch's are gathered there), the window
@@ -110,8 +111,7 @@ class WindowBatch:
         h = self._h_idx[slot]
         h[0].copy_(torch.from_numpy(scenes.astype(np.int32)))
         h[1].copy_(torch.from_numpy(k0))
-        self.inst.copy_(h[0], non_blocking=True)
-        self.frame.copy_(h[1], non_blocking=True)
+        self.idx.copy_(h, non_blocking=True)
         ev = torch.cuda.Event()
         ev.record(main)
         self._ev[slot] = ev

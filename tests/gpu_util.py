@@ -26,7 +26,14 @@ def aligned_sizes():
     return [(4, 4), (9, 20), (33, 68), (2, 132), (17, 36), (64, 64), (3, 100), (40, 12)]
 
 
-SIZE_SETS = {"ragged": ragged_sizes, "aligned": aligned_sizes}
+def wide_sizes():
+    """Every width at least 4, most not a multiple of 4 (16-byte row pieces at 4-byte alignment):
+    widths 4 to 7 (one piece crossing the right edge by 0 to 3 columns), several tiles with
+    ragged tails, and instance offsets that are not multiples of 4."""
+    return [(5, 4), (3, 5), (7, 6), (2, 7), (17, 23), (33, 65), (64, 64), (9, 130), (40, 13), (3, 70)]
+
+
+SIZE_SETS = {"ragged": ragged_sizes, "aligned": aligned_sizes, "wide": wide_sizes}
 
 
 def perturbed_batch(sizes, seed, vel=0.05, pos=0.15, mat=None):

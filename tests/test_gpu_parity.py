@@ -4,8 +4,9 @@ Tolerances (derived in the design notes):
   * mass-spring step, FP32: positions within 1e-5 of the cloth width; velocities within
     max(1e-5 |v|_inf, the worst-case FP32 rounding floor of the spring lengths);
   * CNN frame, FP32 operands: 1e-5 relative (inf-norm) on the new state and on dv;
-  * CNN frame, bf16 operands: 1e-2 relative on dv against the exact FP64 oracle, and close to
-    the emulated-bf16 oracle (same operand rounding, FP64 accumulation);
+  * CNN frame, bf16 operands: 2e-2 relative on dv against the exact FP64 oracle (the bf16
+    scheme's own error: the emulated oracle is 0.6-1.2e-2 from the exact one on these inputs), and
+    close to the emulated-bf16 oracle (same operand rounding, FP64 accumulation);
   * backward: 1e-5 relative on every gradient;
   * FP64 reductions: 1e-12 relative.
 """
@@ -16,7 +17,8 @@ import pytest
 
 import oracle
 from paper_2403_12820_amd import inputs as I
-from tests.gpu_util import SIZE_SETS, dev_tensor, perturbed_batch, ragged_sizes, ms_velocity_floor, rel_inf
+from tests.gpu_util import (SIZE_SETS, dev_tensor, perturbed_batch, ragged_sizes, wide_sizes, ms_velocity_floor,
+                             rel_inf)
 
 pytestmark = pytest.mark.gpu
 
@@ -175,7 +177,7 @@ def test_cnn_forward_fp32_matches_oracle(torch_mod, L, ch, cfg):
     assert rel_inf(dv, dv_ref) <= 1e-5, rel_inf(dv, dv_ref)
 
 
-@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned", "wide"])
 @pytest.mark.parametrize("ch", [16, 32])
 def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch, sizes_kind):
     batch, s0, s1, th = _cnn_inputs(SIZE_SETS[sizes_kind](), 300 + ch, ch, 30.0)
@@ -187,7 +189,8 @@ def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch, sizes_kind):
     dv = _dv_from_state(batch, s1, got, 5e-3)
     e_exact = rel_inf(dv, dv_exact)
     e_emu = rel_inf(dv, dv_emu)
-    assert e_exact <= 1e-2, e_exact
+    # the bf16 operand rounding alone: the emulated oracle is up to 1.2e-2 from the exact one here
+    assert e_exact <= 2e-2, e_exact
     # Same operand rounding as the emulated oracle: the FP32 (GPU) and FP64 (oracle) accumulations
     # differ by ~1e-7 relative, which is enough to send an intermediate feature to the other bf16
     # neighbour now and then. Such a flip moves one head term by at most one bf16 ulp (2^-8 of the
@@ -199,13 +202,44 @@ def test_cnn_forward_bf16_matches_oracle(torch_mod, L, ch, sizes_kind):
     assert np.quantile(per_node, 0.99) <= 2e-4, np.quantile(per_node, 0.99)
 
 
-@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned", "wide"])
 def test_cnn_tile_configs_bitwise_equal(torch_mod, L, sizes_kind):
     for prec in (0, 1):
         batch, s0, s1, th = _cnn_inputs(SIZE_SETS[sizes_kind](), 400, 32, 10.0)
         outs = [_cnn_gpu(L, torch_mod, batch, s0, s1, th, 32, prec, cfg=c) for c in range(4)]
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
+
+
+def _sub_batch(batch, ks):
+    """The instances ks of a batch, as a batch of their own (same parameters, pins and state)."""
+    sls = [batch.instance(k) for k in ks]
+    cnt = np.array([sl.stop - sl.start for sl in sls], np.int64)
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    pick = lambda a: a[list(ks)]
+    return I.Batch(pick(batch.H), pick(batch.W), pick(batch.h), pick(batch.mass), pick(batch.a_ext),
+                   np.concatenate([batch.pin[sl] for sl in sls]), np.concatenate([batch.state[:, sl] for sl in sls], 1),
+                   off, pick(batch.pressure))
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_bf16_row_load_paths_bitwise_equal(torch_mod, L, cfg):
+    """The bf16 frame loads halo rows as aligned 16-byte pieces (every width and offset a multiple
+    of 4), as 16-byte pieces at 4-byte alignment (every width at least 4) or as single floats
+    (otherwise); the plan picks the path. No node's output may depend on it."""
+    sizes = wide_sizes() + [(3, 2)]
+    full, s0, s1, th = _cnn_inputs(sizes, 450, 32, 10.0)
+    cols = lambda a, ks: np.concatenate([a[:, full.instance(k)] for k in ks], 1)
+    # single floats: the whole batch (one cloth is 2 wide)
+    ref = _cnn_gpu(L, torch_mod, full, s0, s1, th, 32, L.PECNN_BF16, cfg=cfg)
+    # 4-byte aligned pieces: every cloth but the 2-wide one
+    ks = list(range(len(sizes) - 1))
+    got = _cnn_gpu(L, torch_mod, _sub_batch(full, ks), cols(s0, ks), cols(s1, ks), th, 32, L.PECNN_BF16, cfg=cfg)
+    assert np.array_equal(got, cols(ref, ks))
+    # aligned pieces: the 64 x 64 cloth and the 5 x 4 one
+    ks = [sizes.index((64, 64)), sizes.index((5, 4))]
+    got = _cnn_gpu(L, torch_mod, _sub_batch(full, ks), cols(s0, ks), cols(s1, ks), th, 32, L.PECNN_BF16, cfg=cfg)
+    assert np.array_equal(got, cols(ref, ks))
 
 
 def test_cnn_config0_rollout_100_steps(torch_mod, L):
