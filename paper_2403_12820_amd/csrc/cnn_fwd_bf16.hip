@@ -13,28 +13,12 @@
 //    head rows repeat the three outputs in every 4-row group, so lane group g finishes segment
 //    g of the quad and a quad's 64 results leave as full-row stores.
 #include "cnn_common.hpp"
+#include "row_pieces.hpp"
 
 namespace pecnn {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-// 16 bytes from a float address that is only 4-byte aligned: the copy states the true alignment,
-// and the target's code generator chooses the access (one 16-byte load on gfx950).
-__device__ __forceinline__ float4 gld4_dword(const float* __restrict__ base, unsigned idx) {
-  float4 v;
-  __builtin_memcpy(&v, reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(float), sizeof(float4));
-  return v;
-}
-
-// Element k of the result is element min(k + sh, 3) of p (sh >= 0).
-__device__ __forceinline__ float4 shift_clamped(float4 p, int sh) {
-  float4 r;
-  r.x = sh == 0 ? p.x : (sh == 1 ? p.y : (sh == 2 ? p.z : p.w));
-  r.y = sh == 0 ? p.y : (sh == 1 ? p.z : p.w);
-  r.z = sh == 0 ? p.z : p.w;
-  r.w = p.w;
-  return r;
-}
 
 // WPE: waves per SIMD the register allocation is held to (3 fits the tiles up to 256 nodes).
 // VEC: how the halo rows load. 1: every plane row starts 16-byte aligned (W and the instance
@@ -461,8 +445,7 @@ static int bf16_cfg_v(const pecnn_plan* plan, int cfg, const float* sp, const fl
 template <int CH, bool A1>
 static int bf16_cfg(const pecnn_plan* plan, int cfg, const float* sp, const float* sc, float* sn,
                     const float* theta, float dt, float alpha, const int32_t* skip, hipStream_t st) {
-  int min_w = plan->W[0];
-  for (int b = 1; b < plan->n; ++b) min_w = min(min_w, plan->W[b]);
+  const int min_w = plan_min_width(plan->W, plan->n);
   if (plan->has_pressure || plan->has_sphere) {
     if (plan->vec4) return bf16_cfg_v<CH, A1, 1, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);
     if (min_w >= 4) return bf16_cfg_v<CH, A1, 2, true>(plan, cfg, sp, sc, sn, theta, dt, alpha, skip, st);

@@ -7,6 +7,7 @@
 // the current tile is computed, so HBM latency hides behind the spring arithmetic. Each XCD
 // walks a contiguous tile range, so halo rows shared by neighbouring tiles meet in one L2.
 #include "common.hpp"
+#include "row_pieces.hpp"
 
 #include <type_traits>
 
@@ -20,8 +21,10 @@ __device__ constexpr Spring kSprings[12] = {
     {1, 1, 1}, {1, -1, 1}, {-1, 1, 1}, {-1, -1, 1},
     {0, 2, 2}, {0, -2, 2}, {2, 0, 2}, {-2, 0, 2}};
 
-// VEC: every plane row starts 16-byte aligned (W and the instance offsets are multiples of 4),
-// so the tile rows load as 16-byte pieces; otherwise as single floats.
+// VEC: how the tile rows load. 1: every plane row starts 16-byte aligned (W and the instance
+// offsets are multiples of 4), so as aligned 16-byte pieces. 2: every cloth is at least 4 wide,
+// so as 16-byte pieces at 4-byte alignment, the piece that would cross the right edge taken at
+// W - 4 and shifted into place in registers. 0: as single floats.
 // EXT: some instance of the batch has a pressure (eq. 3) or a sphere in its constraint; the
 // others skip both uniformly.
 // PAIR: instead of the springs, one frame of the paper's own cell read literally (section 3.2):
@@ -35,7 +38,7 @@ struct PairArgs {
   const int32_t* skip;   // instances to leave alone (fallen back), or null
 };
 
-template <int TX, int TY, int RY, bool VEC, bool EXT, bool PAIR = false>
+template <int TX, int TY, int RY, int VEC, bool EXT, bool PAIR = false>
 __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const InstDev* __restrict__ inst, const int32_t* __restrict__ prefix, int n_inst, int n_tiles,
     const uint8_t* __restrict__ pin, const float* __restrict__ s_in, float* __restrict__ s_out,
@@ -106,9 +109,12 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
         const int gi = min(max(r0 + rr - 2, 0), I.H - 1);
         const int col = c0 + 4 * q;
         const unsigned rb = (unsigned)(c * (int)N + (int)I.off + gi * I.W);
-        if constexpr (VEC) {
+        if constexpr (VEC == 1) {
           // a piece right of the grid loads the last in-grid piece (never a spring end)
           pv[i] = gld(reinterpret_cast<const float4*>(s_in), rb + (unsigned)min(col, I.W - 4));
+        } else if constexpr (VEC == 2) {
+          // the four columns from min(col, W - 4): inside the row for every W >= 4
+          pv[i] = gld4_dword(s_in, rb + (unsigned)min(col, I.W - 4));
         } else {
           pv[i] = make_float4(gld(s_in, rb + min(col, I.W - 1)), gld(s_in, rb + min(col + 1, I.W - 1)),
                               gld(s_in, rb + min(col + 2, I.W - 1)), gld(s_in, rb + min(col + 3, I.W - 1)));
@@ -136,13 +142,20 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
       }
     }
   };
-  auto stage = [&]() {
+  // Registers -> LDS for the tile whose first column is sc0 in a cloth sW wide.
+  auto stage = [&](int sW, int sc0) {
 #pragma unroll
     for (int i = 0; i < NVT; ++i) {
       const int j = tid + NT * i;
       if (NV % NT == 0 || j < NV) {
         const int row = j / QV, q = j - (j / QV) * QV;
         const int c = row / HY, rr = row - (row / HY) * HY;
+        if constexpr (VEC == 2) {
+          if (sc0 + TX > sW) {  // uniform: a tile crossing the right edge of the grid
+            const int col = sc0 + 4 * q;
+            pv[i] = shift_clamped(pv[i], col - min(col, sW - 4));
+          }
+        }
         *reinterpret_cast<float4*>(&lds[c * PLN + rr * RS + 4 + 4 * q]) = pv[i];
       }
     }
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const int rc0 = r0, cc0 = c0;
     // every prefetched register is consumed here on every path, so the next loads that reuse
     // them never wait on older stores
-    stage();
+    stage(Ic.W, cc0);
     __syncthreads();
     // prefetch the next tile (after the last tile, a reload of this one: no branch around it)
     const int tn = next_tile(t + stride);
@@ -364,12 +377,15 @@ static void launch_ms(const pecnn_plan* plan, int slot, const MsParamsDev& P, co
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TX * (TY / RY)), 0, st, plan->d_inst, plan->d_prefix[slot], plan->n,
                        n_tiles, plan->pin, in, out, plan->total, P, active, PairArgs{}, plan->d_sphere);
   };
+  const int vec = plan->vec4 ? 1 : (plan_min_width(plan->W, plan->n) >= 4 ? 2 : 0);
   if (plan->has_pressure || plan->has_sphere) {
-    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, true>);
-    else go(ms_step_kernel<TX, TY, RY, false, true>);
+    if (vec == 1) go(ms_step_kernel<TX, TY, RY, 1, true>);
+    else if (vec == 2) go(ms_step_kernel<TX, TY, RY, 2, true>);
+    else go(ms_step_kernel<TX, TY, RY, 0, true>);
   } else {
-    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, false>);
-    else go(ms_step_kernel<TX, TY, RY, false, false>);
+    if (vec == 1) go(ms_step_kernel<TX, TY, RY, 1, false>);
+    else if (vec == 2) go(ms_step_kernel<TX, TY, RY, 2, false>);
+    else go(ms_step_kernel<TX, TY, RY, 0, false>);
   }
 }
 
@@ -383,12 +399,15 @@ static void launch_pair(const pecnn_plan* plan, int slot, const PairArgs& pa, co
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TX * (TY / RY)), 0, st, plan->d_inst, plan->d_prefix[slot], plan->n,
                        n_tiles, plan->pin, in, out, plan->total, P, (const uint8_t*)nullptr, pa, plan->d_sphere);
   };
+  const int vec = plan->vec4 ? 1 : (plan_min_width(plan->W, plan->n) >= 4 ? 2 : 0);
   if (plan->has_pressure || plan->has_sphere) {
-    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, true, true>);
-    else go(ms_step_kernel<TX, TY, RY, false, true, true>);
+    if (vec == 1) go(ms_step_kernel<TX, TY, RY, 1, true, true>);
+    else if (vec == 2) go(ms_step_kernel<TX, TY, RY, 2, true, true>);
+    else go(ms_step_kernel<TX, TY, RY, 0, true, true>);
   } else {
-    if (plan->vec4) go(ms_step_kernel<TX, TY, RY, true, false, true>);
-    else go(ms_step_kernel<TX, TY, RY, false, false, true>);
+    if (vec == 1) go(ms_step_kernel<TX, TY, RY, 1, false, true>);
+    else if (vec == 2) go(ms_step_kernel<TX, TY, RY, 2, false, true>);
+    else go(ms_step_kernel<TX, TY, RY, 0, false, true>);
   }
 }
 

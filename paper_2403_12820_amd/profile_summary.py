@@ -28,8 +28,8 @@ import os
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
-    "cnn_fwd_bf16": ("cnn_fwd_bf16.hip", "cnn_common.hpp", "common.hpp"),
-    "ms_step": ("ms_step.hip", "common.hpp"),
+    "cnn_fwd_bf16": ("cnn_fwd_bf16.hip", "cnn_common.hpp", "common.hpp", "row_pieces.hpp"),
+    "ms_step": ("ms_step.hip", "common.hpp", "row_pieces.hpp"),
     "cnn_bwd": ("cnn_bwd.hip", "cnn_bwd_tile.hip", "cnn_bwd_table.hpp", "cnn_common.hpp", "common.hpp"),
 }
 

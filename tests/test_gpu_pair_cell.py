@@ -55,7 +55,7 @@ def _increment(batch, s, out):
     return d
 
 
-@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned", "wide"])
 def test_pair_forward_matches_oracle(L, sizes_kind):
     batch, th = _inputs(SIZE_SETS[sizes_kind]() + [(32, 32)], 800)
     got = _forward(L, batch, th)

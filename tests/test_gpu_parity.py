@@ -51,7 +51,7 @@ def _ms_gpu(L, torch, batch, s, n_steps=1, cfg=None, mat=MAT, active=None):
 
 
 # ------------------------------------------------------------------ mass-spring step
-@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned", "wide"])
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 def test_ms_step_matches_oracle(torch_mod, L, cfg, sizes_kind):
     sizes = SIZE_SETS[sizes_kind]() + [(32, 32)]
@@ -64,7 +64,7 @@ def test_ms_step_matches_oracle(torch_mod, L, cfg, sizes_kind):
     assert np.abs(got[3:] - ref[3:]).max() <= tol_v, (np.abs(got[3:] - ref[3:]).max(), tol_v)
 
 
-@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned"])
+@pytest.mark.parametrize("sizes_kind", ["ragged", "aligned", "wide"])
 def test_ms_tile_configs_bitwise_equal(torch_mod, L, sizes_kind):
     batch = perturbed_batch(SIZE_SETS[sizes_kind](), seed=101)
     outs = [_ms_gpu(L, torch_mod, batch, batch.state, 3, cfg) for cfg in range(5)]
@@ -240,6 +240,20 @@ def test_bf16_row_load_paths_bitwise_equal(torch_mod, L, cfg):
     ks = [sizes.index((64, 64)), sizes.index((5, 4))]
     got = _cnn_gpu(L, torch_mod, _sub_batch(full, ks), cols(s0, ks), cols(s1, ks), th, 32, L.PECNN_BF16, cfg=cfg)
     assert np.array_equal(got, cols(ref, ks))
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+def test_ms_row_load_paths_bitwise_equal(torch_mod, L, cfg):
+    """The mass-spring step picks its row loads like the bf16 frame (aligned pieces, pieces at
+    4-byte alignment, single floats); three steps of each node must not depend on the path."""
+    sizes = wide_sizes() + [(3, 2)]
+    full = perturbed_batch(sizes, seed=460)
+    cols = lambda a, ks: np.concatenate([a[:, full.instance(k)] for k in ks], 1)
+    ref = _ms_gpu(L, torch_mod, full, full.state, 3, cfg)
+    for ks in (list(range(len(sizes) - 1)), [sizes.index((64, 64)), sizes.index((5, 4))]):
+        sub = _sub_batch(full, ks)
+        got = _ms_gpu(L, torch_mod, sub, sub.state, 3, cfg)
+        assert np.array_equal(got, cols(ref, ks)), ks
 
 
 def test_cnn_config0_rollout_100_steps(torch_mod, L):
