@@ -293,10 +293,12 @@ int pecnn_workspace_bytes(const pecnn_plan* plan, const pecnn_model* model, int3
                           size_t* bytes);
 
 /* Time every tile configuration of the mass-spring step and the CNN cell on this batch
-   (synchronous: runs 'reps' timed launches of each on 'stream' using the given buffers, which
-   are overwritten) and store the fastest in the plan. s_a, s_b, s_c: device [6][N_total]
-   scratch states (contents preserved are not guaranteed). ms_ms/cnn_ms (host, nullable, length
-   5 and 4) receive the mean milliseconds per launch of each configuration. */
+   (synchronous: three interleaved rounds, each running 'reps' timed launches of every
+   configuration on 'stream' using the given buffers, which are overwritten) and store the
+   fastest in the plan; a configuration's time is its best round, so a clock still ramping under
+   the new load favours none. s_a, s_b, s_c: device [6][N_total] scratch states (contents
+   preserved are not guaranteed). ms_ms/cnn_ms (host, nullable, length 5 and 4) receive the
+   best round's mean milliseconds per launch of each configuration. */
 int pecnn_autotune(pecnn_plan* plan, const cloth_ms_params* p, const pecnn_model* model,
                    float* s_a, float* s_b, float* s_c, int32_t reps, float* ms_ms, float* cnn_ms,
                    void* stream);

@@ -961,36 +961,51 @@ static int time_launches(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps,
   return PECNN_OK;
 }
 
+// The configurations are timed in interleaved rounds (each round times every configuration
+// once) and each keeps its best round: the chip's clock ramps for a few hundred milliseconds under
+// a new load, and configurations timed one after another would favour the later ones.
+constexpr int kTuneRounds = 3;
+
 static int autotune_impl(pecnn_plan* p, const cloth_ms_params* prm, const pecnn_model* m, float* s_a, float* s_b,
                          float* s_c, int reps, float* ms_ms, float* cnn_ms, hipStream_t st, hipEvent_t e0,
                          hipEvent_t e1) {
   const MsParamsDev P = ms_params_dev(prm);
-  float best = 1e30f;
-  int best_cfg = p->ms_cfg;
-  for (int c = 0; c < kNumMsCfg; ++c) {
-    float t = 0.f;
-    int rc = time_launches(st, e0, e1, reps, &t, [&](int r) {
-      return ms_step_once(p, c, P, (r & 1) ? s_b : s_a, (r & 1) ? s_a : s_b, nullptr, st);
-    });
-    if (rc) return rc;
-    if (ms_ms) ms_ms[c] = t;
-    if (t < best) { best = t; best_cfg = c; }
-  }
-  p->ms_cfg = best_cfg;
-  if (!m) return PECNN_OK;
-  best = 1e30f;
-  best_cfg = p->cnn_cfg;
+  float ms_t[kNumMsCfg], cnn_t[kNumCnnCfg];
+  for (int c = 0; c < kNumMsCfg; ++c) ms_t[c] = 1e30f;
+  for (int c = 0; c < kNumCnnCfg; ++c) cnn_t[c] = 1e30f;
   float* bs[3] = {s_a, s_b, s_c};
-  for (int c = 0; c < kNumCnnCfg; ++c) {
-    float t = 0.f;
-    int rc = time_launches(st, e0, e1, reps, &t, [&](int r) {
-      return cnn_forward_launch(p, c, m, bs[r % 3], bs[(r + 1) % 3], bs[(r + 2) % 3], nullptr, st);
-    });
-    if (rc) return rc;
-    if (cnn_ms) cnn_ms[c] = t;
-    if (t < best) { best = t; best_cfg = c; }
+  for (int round = 0; round < kTuneRounds; ++round) {
+    for (int c = 0; c < kNumMsCfg; ++c) {
+      float t = 0.f;
+      int rc = time_launches(st, e0, e1, reps, &t, [&](int r) {
+        return ms_step_once(p, c, P, (r & 1) ? s_b : s_a, (r & 1) ? s_a : s_b, nullptr, st);
+      });
+      if (rc) return rc;
+      ms_t[c] = std::min(ms_t[c], t);
+    }
+    if (!m) continue;
+    for (int c = 0; c < kNumCnnCfg; ++c) {
+      float t = 0.f;
+      int rc = time_launches(st, e0, e1, reps, &t, [&](int r) {
+        return cnn_forward_launch(p, c, m, bs[r % 3], bs[(r + 1) % 3], bs[(r + 2) % 3], nullptr, st);
+      });
+      if (rc) return rc;
+      cnn_t[c] = std::min(cnn_t[c], t);
+    }
   }
-  p->cnn_cfg = best_cfg;
+  int best = 0;
+  for (int c = 0; c < kNumMsCfg; ++c) {
+    if (ms_ms) ms_ms[c] = ms_t[c];
+    if (ms_t[c] < ms_t[best]) best = c;
+  }
+  p->ms_cfg = best;
+  if (!m) return PECNN_OK;
+  best = 0;
+  for (int c = 0; c < kNumCnnCfg; ++c) {
+    if (cnn_ms) cnn_ms[c] = cnn_t[c];
+    if (cnn_t[c] < cnn_t[best]) best = c;
+  }
+  p->cnn_cfg = best;
   return PECNN_OK;
 }
 
