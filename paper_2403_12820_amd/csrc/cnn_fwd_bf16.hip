@@ -24,7 +24,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // VEC: how the halo rows load. 1: every plane row starts 16-byte aligned (W and the instance
 // offsets are multiples of 4), so as aligned 16-byte pieces. 2: every instance is at least 4
 // wide, so as 16-byte pieces at 4-byte alignment, the piece that would cross the right edge of
-// the grid taken at W - 4 and its values moved into place in registers. 0: as single floats.
+// the grid taken at W - 4 and its values moved into place in LDS after staging. 0: as single
+// floats.
 // EXT: some instance of the batch has a pressure (eq. 3), added as a known external force, or a
 // sphere in the constraint of eq. (5); the others skip both uniformly.
 template <int CH, int TX, int TY, bool A1, int WPE, int VEC, bool EXT>
@@ -177,9 +178,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
   };
 
-  // Registers -> LDS: FP32 S^k, FP32 position differences in time, bf16 velocity planes, for
-  // the tile whose first column is sc0 in an instance sW wide.
-  auto stage = [&](int sW, int sc0) {
+  // Registers -> LDS: FP32 S^k, FP32 position differences in time, bf16 velocity planes.
+  auto stage = [&]() {
 #pragma unroll
     for (int i = 0; i < NVT; ++i) {
       const int j = tid + 256 * i;
@@ -187,15 +187,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         const int row = j / QV, q = j - (j / QV) * QV;
         const int c = row / HY, rr = row - (row / HY) * HY;
         const int e = rr * RS + 4 + 4 * q;
-        if constexpr (VEC == 2) {
-          if (sc0 + TX > sW) {  // uniform: a tile crossing the right edge of the grid
-            // the piece holds columns b .. b + 3, b = min(col, W - 4); column col + k wants
-            // column min(col + k, W - 1), i.e. element min(k + sh, 3) with sh = col - b
-            const int col = sc0 + 4 * q, sh = col - min(col, sW - 4);
-            pS[i] = shift_clamped(pS[i], sh);
-            pP[i] = shift_clamped(pP[i], sh);
-          }
-        }
 
         *reinterpret_cast<float4*>(&tS[c * PLN + e]) = pS[i];
         const float4 d = make_float4(pS[i].x - pP[i].x, pS[i].y - pP[i].y, pS[i].z - pP[i].z, pS[i].w - pP[i].w);
@@ -246,7 +237,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const int rc0 = r0, cc0 = c0;
     // every prefetched register is consumed here on every path, so the next loads that reuse
     // them never wait on older stores
-    stage(Ic.W, cc0);
+    stage();
     __syncthreads();
     if (VEC == 1 && cc0 + TX > Ic.W) {
       // a tile crossing the right edge of the grid: its 16-byte pieces right of the edge hold
@@ -259,6 +250,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         if (pl < 6) tS[pl * PLN + o] = tS[pl * PLN + o - 1];
         else if (pl < 9) tD[(pl - 6) * PLN + o] = tD[(pl - 6) * PLN + o - 1];
         else tV[(pl - 9) * PLN + o] = tV[(pl - 9) * PLN + o - 1];
+      }
+      __syncthreads();
+    }
+    if (VEC == 2 && cc0 + TX > Ic.W) {
+      // a tile crossing the right edge of the grid, its pieces loaded from min(col, W - 4): the
+      // piece holding the last in-grid column sits sh columns right of its source (row_pieces.hpp)
+      const int e = Ic.W - cc0, qs = (e - 1) >> 2, sh = 4 * qs + 4 - e;
+      for (int it = tid; it < 15 * HY; it += 256) {
+        const int pl = it / HY, rr = it - (it / HY) * HY;
+        const int o = rr * RS + 4 + 4 * qs;
+        if (pl < 6) shift_piece_lds(&tS[pl * PLN + o], sh);
+        else if (pl < 9) shift_piece_lds(&tD[(pl - 6) * PLN + o], sh);
+        else shift_piece_lds(&tV[(pl - 9) * PLN + o], sh);
       }
       __syncthreads();
     }

@@ -24,7 +24,7 @@ __device__ constexpr Spring kSprings[12] = {
 // VEC: how the tile rows load. 1: every plane row starts 16-byte aligned (W and the instance
 // offsets are multiples of 4), so as aligned 16-byte pieces. 2: every cloth is at least 4 wide,
 // so as 16-byte pieces at 4-byte alignment, the piece that would cross the right edge taken at
-// W - 4 and shifted into place in registers. 0: as single floats.
+// W - 4 and shifted into place in LDS after staging. 0: as single floats.
 // EXT: some instance of the batch has a pressure (eq. 3) or a sphere in its constraint; the
 // others skip both uniformly.
 // PAIR: instead of the springs, one frame of the paper's own cell read literally (section 3.2):
@@ -142,20 +142,13 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
       }
     }
   };
-  // Registers -> LDS for the tile whose first column is sc0 in a cloth sW wide.
-  auto stage = [&](int sW, int sc0) {
+  auto stage = [&]() {
 #pragma unroll
     for (int i = 0; i < NVT; ++i) {
       const int j = tid + NT * i;
       if (NV % NT == 0 || j < NV) {
         const int row = j / QV, q = j - (j / QV) * QV;
         const int c = row / HY, rr = row - (row / HY) * HY;
-        if constexpr (VEC == 2) {
-          if (sc0 + TX > sW) {  // uniform: a tile crossing the right edge of the grid
-            const int col = sc0 + 4 * q;
-            pv[i] = shift_clamped(pv[i], col - min(col, sW - 4));
-          }
-        }
         *reinterpret_cast<float4*>(&lds[c * PLN + rr * RS + 4 + 4 * q]) = pv[i];
       }
     }
@@ -188,8 +181,18 @@ __global__ __launch_bounds__(TX*(TY / RY)) void ms_step_kernel(
     const int rc0 = r0, cc0 = c0;
     // every prefetched register is consumed here on every path, so the next loads that reuse
     // them never wait on older stores
-    stage(Ic.W, cc0);
+    stage();
     __syncthreads();
+    if (VEC == 2 && cc0 + TX > Ic.W) {
+      // a tile crossing the right edge of the grid, its pieces loaded from min(col, W - 4): the
+      // piece holding the last in-grid column sits sh columns right of its source (row_pieces.hpp)
+      const int e = Ic.W - cc0, qs = (e - 1) >> 2, sh = 4 * qs + 4 - e;
+      for (int it = tid; it < 6 * HY; it += NT) {
+        const int pl = it / HY, rr = it - (it / HY) * HY;
+        shift_piece_lds(&lds[pl * PLN + rr * RS + 4 + 4 * qs], sh);
+      }
+      __syncthreads();
+    }
     // prefetch the next tile (after the last tile, a reload of this one: no branch around it)
     const int tn = next_tile(t + stride);
     if (tn >= 0) coords(tn, I, r0, c0);
