@@ -1,6 +1,6 @@
 """The committed rocprofv3 summaries: each names the command that made it, the commands run
 committed files only, and every counter summary was taken from the kernel sources as they are
-now (its source hash matches), so the roofline figures that quote it describe this build."""
+now (its source hash matches), so the roofline figures that quote it describe these kernels."""
 import glob
 import os
 
