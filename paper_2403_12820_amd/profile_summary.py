@@ -167,6 +167,25 @@ def _sq(args):
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
+def _markers(args):
+    """roctx ranges of a run (host time from push to pop), by name, in order of first use."""
+    per, order = {}, []
+    for r in csv.DictReader(open(args.csv)):
+        name = r["Function"]
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        if name not in per:
+            per[name] = []
+            order.append(name)
+        per[name].append(d)
+    lines = ["roctx ranges (host time from push to pop)", "command: " + args.command, "",
+             "| range | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for name in order:
+        d = per[name]
+        lines.append("| %s | %d | %.1f | %.1f | %.1f |" % (name, len(d), sum(d) / len(d), min(d), max(d)))
+    lines += ["note: " + n for n in args.note]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -201,8 +220,13 @@ def main():
     q.add_argument("--command-b", required=True)
     q.add_argument("--simds", type=int, default=1024)
     q.add_argument("--xcds", type=int, default=8)
+    m = sub.add_parser("markers")
+    m.add_argument("csv", help="marker_api_trace.csv")
+    m.add_argument("out")
+    m.add_argument("--command", required=True)
+    m.add_argument("--note", action="append", default=[], help="a line of context (repeatable)")
     a = ap.parse_args()
-    {"stats": _stats, "traffic": _traffic, "sq": _sq}[a.cmd](a)
+    {"stats": _stats, "traffic": _traffic, "sq": _sq, "markers": _markers}[a.cmd](a)
 
 
 if __name__ == "__main__":
